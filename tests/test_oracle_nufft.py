@@ -1,0 +1,160 @@
+"""Pins of the oracle's measurement operator against things other than itself.
+
+* Kaiser-Bessel: I0 against scipy's Bessel routine; phihat against numerical
+  quadrature of the kernel (the closed form is not re-typed).
+* Phi against the exact Fourier sum it approximates (brute force), within the
+  interpolation error of the kernel width.
+* Phi^dagger against Phi by the adjoint identity <Phi x, w> = <x, Phi^dagger w>.
+* Special cases: a centred delta image gives y = 1/K everywhere; a shifted delta
+  gives a pure phase; a visibility on a grid node has weights phi(integers).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.special
+
+import workloads as W
+from oracle import kaiser_bessel as kb
+from oracle import nufft
+
+
+def test_i0_matches_library():
+    z = np.linspace(0.0, 30.0, 301)
+    np.testing.assert_allclose(kb.i0(z), scipy.special.i0(z), rtol=2e-15)
+
+
+@pytest.mark.parametrize("J,K", [(6, 128), (8, 512), (8, 2048)])
+def test_phihat_is_fourier_transform_of_phi(J, K):
+    b = kb.beta(J)
+    for l in (0, 1, K // 8, K // 4 - 1):
+        val, _ = scipy.integrate.quad(
+            lambda t: kb.phi(t, J, b) * math.cos(2 * math.pi * t * l / K),
+            -J / 2, J / 2, epsabs=1e-14, epsrel=1e-13, limit=200)
+        assert abs(val - kb.phihat(l, J, K, b)) <= 1e-11 * abs(val)
+
+
+def test_kernel_shape():
+    for J in (4, 6, 8):
+        assert kb.phi(0.0, J) == pytest.approx(1.0, abs=1e-15)
+        assert kb.phi(J / 2 + 1e-9, J) == 0.0
+        t = np.linspace(-J / 2, J / 2, 101)
+        np.testing.assert_allclose(kb.phi(t, J), kb.phi(-t, J), rtol=0, atol=1e-15)
+        assert np.all(np.diff(kb.phi(t[50:], J)) < 0)
+
+
+def test_window_rule():
+    J = 8
+    g = np.array([0.0, 0.5, 3.999, 4.0, -4.0, 1023.3])
+    a0 = kb.window(g, J)
+    for gi, ai in zip(g, a0):
+        taps = ai + np.arange(J)
+        assert np.all(taps > gi - J / 2) and np.all(taps <= gi + J / 2)
+
+
+@pytest.mark.parametrize("J,tol", [(6, 2e-5), (8, 5e-7)])
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_phi_matches_direct_sum(J, tol, n):
+    g = W.rng(100, 0, n * 10 + J)
+    M = 4 * n
+    uv = W.coverage(M, g)
+    x = W.random_complex((n, n), g)
+    op = nufft.Operator(n, uv, J)
+    y = op.phi(x)
+    yd = nufft.direct(x, uv)
+    assert np.linalg.norm(y - yd) <= tol * np.linalg.norm(yd)
+    # The adjoint approximates the exact adjoint sum to the same accuracy.
+    w = W.random_complex(M, g)
+    xa = op.phi_adj(w)
+    xd = nufft.direct_adj(w, uv, n)
+    assert np.linalg.norm(xa - xd) <= tol * np.linalg.norm(xd)
+
+
+def test_phi_uniform_coverage_edges():
+    """Points anywhere in [-pi, pi), including the edges, are interpolated accurately."""
+    n, J = 32, 8
+    g = W.rng(100, 1)
+    uv = g.uniform(-math.pi, math.pi, size=(300, 2))
+    uv[:4] = [[-math.pi, -math.pi], [-math.pi, 0.0], [0.0, math.pi - 1e-12], [3.14, -3.14]]
+    x = W.random_complex((n, n), g)
+    op = nufft.Operator(n, uv, J)
+    yd = nufft.direct(x, uv)
+    assert np.linalg.norm(op.phi(x) - yd) <= 5e-7 * np.linalg.norm(yd)
+
+
+@pytest.mark.parametrize("J", [6, 8])
+def test_adjoint_identity(J):
+    n, M = 32, 500
+    g = W.rng(100, 2, J)
+    op = nufft.Operator(n, W.coverage(M, g), J)
+    x = W.random_complex((n, n), g)
+    w = W.random_complex(M, g)
+    lhs = np.vdot(op.phi(x), w)
+    rhs = np.vdot(x.ravel(), op.phi_adj(w).ravel())
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_centred_delta_and_shifted_delta():
+    n, J, M = 32, 8, 200
+    g = W.rng(100, 3)
+    uv = W.coverage(M, g)
+    op = nufft.Operator(n, uv, J)
+    K = op.K
+    x = np.zeros((n, n))
+    x[n // 2, n // 2] = 1.0
+    np.testing.assert_allclose(op.phi(x), np.full(M, 1.0 / K), rtol=0, atol=2e-7 / K)
+    p, q = 3, 27
+    x = np.zeros((n, n))
+    x[p, q] = 1.0
+    expect = np.exp(-1j * (uv[:, 0] * (p - n // 2) + uv[:, 1] * (q - n // 2))) / K
+    np.testing.assert_allclose(op.phi(x), expect, rtol=0, atol=5e-7 / K)
+
+
+def test_visibility_on_grid_node_has_integer_offset_weights():
+    n, J = 16, 6
+    K = 2 * n
+    a, b = 5, -7
+    uv = np.array([[2 * math.pi * a / K, 2 * math.pi * b / K]])
+    G = nufft.g_matrix(uv, K, J)
+    row = G.toarray()[0].reshape(K, K)
+    # Offsets t = g - a' for the J window taps; on a node they are integers.
+    taps = np.arange(kb.window(a, J), kb.window(a, J) + J)
+    w = kb.phi(a - taps, J)
+    expect = np.zeros((K, K))
+    for i, ta in enumerate(taps):
+        for j, tb in enumerate(taps - a + b):
+            expect[ta % K, tb % K] = w[i] * w[j]
+    np.testing.assert_allclose(row, expect, rtol=0, atol=1e-15)
+
+
+def test_unitary_fft_scaling():
+    g = W.rng(100, 4)
+    X = W.random_complex((64, 64), g)
+    assert np.linalg.norm(np.fft.fft2(X) / 64) == pytest.approx(np.linalg.norm(X), rel=1e-14)
+
+
+def test_sampled_rows_equal_full_operator():
+    n, J, M = 32, 8, 300
+    g = W.rng(100, 5)
+    uv = W.coverage(M, g)
+    x = W.random_complex((n, n), g)
+    op = nufft.Operator(n, uv, J)
+    idx = np.array([0, 7, 99, 299])
+    np.testing.assert_allclose(nufft.phi_sampled(x, uv, J, idx), op.phi(x)[idx], rtol=1e-13)
+
+
+def test_gram_spectrum_bounded():
+    """Phi^dagger Phi is Hermitian PSD; its top eigenvalue is finite (sets CG's conditioning)."""
+    n, J, M = 8, 6, 128
+    g = W.rng(100, 6)
+    op = nufft.Operator(n, W.coverage(M, g), J)
+    cols = []
+    for k in range(n * n):
+        e = np.zeros(n * n, dtype=np.complex128)
+        e[k] = 1
+        cols.append(op.phi_adj(op.phi(e.reshape(n, n))).ravel())
+    A = np.array(cols).T
+    np.testing.assert_allclose(A, A.conj().T, atol=1e-13)
+    ev = np.linalg.eigvalsh(A)
+    assert ev.min() > -1e-12

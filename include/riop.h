@@ -1,0 +1,228 @@
+/*
+ * riop.h -- C interface of the MI355X (gfx950) library for the SDMM
+ * radio-interferometric imaging hot path of Carrillo, McEwen & Wiaux,
+ * "PURIFY: a new approach to radio-interferometric imaging" (arXiv:1307.4370).
+ *
+ * The library solves (Sec. 3.3, eq. delta; Sec. 4.3, eq. cvx2)
+ *
+ *     min ||W Psi^dagger x||_1  subject to  ||y - Phi x||_2 <= eps,  x >= 0
+ *
+ * with SDMM (Sec. 4.4, Algorithm 1), and exposes the linear operators it is
+ * built from:
+ *
+ *   Phi         = G F D Z        measurement operator (Sec. 5, eq. opmodel; B = I)
+ *   Phi^dagger  = Z^T D F^dagger G^T
+ *   Psi^dagger  SARA analysis: Dirac plus Daubechies Db1..Db8 (Sec. 3.3), scaled
+ *               by 1/sqrt(q) so that Psi Psi^dagger = I (Parseval, Sec. 4.4)
+ *   Psi         SARA synthesis
+ *
+ * Conventions shared by every call
+ *   - Data pointers are device pointers (hipMalloc'd or torch CUDA/HIP tensors)
+ *     unless a comment says "host".  The caller owns every data buffer and must
+ *     keep it alive until the work queued on `stream` has finished.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.  All
+ *     calls only enqueue work on `stream` and return, except where noted.
+ *   - Complex numbers are interleaved (re, im) pairs of the plan's real type:
+ *     float for RIOP_F32 (8 bytes per complex), double for RIOP_F64 (16 bytes).
+ *   - An image x is n x n, row-major: x[p * n + q].  Pixel p sits at offset
+ *     p - n/2 from the image centre; u pairs with the row index p, v with q.
+ *   - Visibilities are in the caller's order (the order of `uv` at plan
+ *     creation) unless an entry point says "plan order".
+ *   - (u, v) are continuous coordinates in radians per pixel in [-pi, pi]
+ *     (pi * (spatial frequency) / (Nyquist frequency)); the oversampled grid
+ *     coordinate is g = u K / (2 pi) with K = 2n.
+ *   - Coefficients alpha of Psi^dagger are q planes of n x n (q = number of bits
+ *     set in dict_mask), in increasing basis order (Dirac, Db1, ..., Db8); a
+ *     wavelet plane holds the L-level periodised 2-D DWT in the Mallat layout
+ *     (low-low in the top-left corner).
+ *   - A plan is not re-entrant: calls on one plan must not overlap in time
+ *     (use one plan per stream).  Plans on different devices are independent;
+ *     a plan is bound to the device current at its creation.
+ *   - Errors: functions return a riop_status.  On failure nothing has been
+ *     enqueued that writes caller buffers, no memory is leaked, and
+ *     riop_last_error() returns a message for the calling thread.  Errors
+ *     raised by the GPU itself (e.g. a device fault) surface as RIOP_EDEVICE
+ *     from the next call that synchronises.
+ */
+#ifndef RIOP_H
+#define RIOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct riop_plan riop_plan;
+
+typedef enum {
+    RIOP_OK = 0,
+    RIOP_EINVAL = -1,     /* bad argument value (NULL, out-of-range uv, ...) */
+    RIOP_ESHAPE = -2,     /* inconsistent sizes */
+    RIOP_ENOMEM = -3,     /* device allocation failed */
+    RIOP_EDEVICE = -4,    /* HIP runtime error */
+    RIOP_ENOTSUP = -5,    /* valid but unsupported configuration */
+    RIOP_ENONFINITE = -6  /* a NaN or Inf reached a norm or the input */
+} riop_status;
+
+enum { RIOP_F32 = 1, RIOP_F64 = 2 };
+
+/* Plan description.
+ *   n          image side; even, 8 <= n <= 8192, divisible by 2^levels
+ *   oversample grid oversampling per axis (k of Sec. 5); must be 2
+ *   M          number of visibilities, 0 <= M < 2^31
+ *   J          Kaiser-Bessel kernel width in grid cells; even, 2 <= J <= 16
+ *   levels     wavelet levels, 1 <= levels
+ *   dict_mask  bit 0 Dirac, bit k Daubechies k (k = 1..8); nonzero, < 2^9
+ *   prec       RIOP_F32: float storage and arithmetic with double-precision
+ *              norms, dot products and CG scalars; RIOP_F64: double throughout
+ *   tile       gridding tile side in grid cells (power of two, 8..64, dividing
+ *              K = 2n); 0 selects the library's choice
+ */
+typedef struct {
+    int32_t n;
+    int32_t oversample;
+    int64_t M;
+    int32_t J;
+    int32_t levels;
+    uint32_t dict_mask;
+    int32_t prec;
+    int32_t tile;
+    int32_t reserved[7];  /* must be zero */
+} riop_desc;
+
+/* Read-only facts about a plan, filled by riop_plan_info. */
+typedef struct {
+    int32_t n, K, J, levels, q, prec;
+    int64_t M;
+    int32_t tile;           /* tile side in grid cells */
+    int32_t ntiles;         /* (K / tile)^2 */
+    int32_t nunits;         /* gridding work units (tile, visibility chunk) */
+    int32_t kernel_degree;  /* degree of the per-tap kernel polynomial */
+    double kb_beta;         /* Kaiser-Bessel shape parameter */
+    double kernel_fit_err;  /* max |polynomial - kernel| found at plan time */
+    int64_t device_bytes;   /* device memory held by the plan */
+} riop_info;
+
+/* Create a plan for one coverage.
+ *   desc    plan description (host)
+ *   uv      device, M x 2 reals of the plan's type: (u_m, v_m) pairs
+ *   stream  queue for the set-up kernels; the call synchronises `stream`
+ *           before returning (it reads back validation flags and bin sizes)
+ *   out     receives the plan (host)
+ * Builds G's sparsity pattern on the device (Sec. 5: "G is highly sparse"):
+ * every visibility's J x J window, binned by grid tile with a stable counting
+ * sort.  uv outside [-pi, pi] or non-finite -> RIOP_EINVAL. */
+riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream,
+                             riop_plan **out);
+
+/* Free a plan and everything it owns.  Waits for the plan's queued work. NULL is a no-op. */
+riop_status riop_plan_destroy(riop_plan *plan);
+
+riop_status riop_plan_info(const riop_plan *plan, riop_info *info /* host */);
+
+/* Plan-order layout of the visibilities (for tests of the binning).
+ *   perm        device int32[M]: perm[i] = caller index of the i-th visibility
+ *               in plan order (sorted by tile, then by caller index)
+ *   cell        device uint32[M]: first window cell of the i-th visibility,
+ *               a0 | (b0 << 16) with a0, b0 in [0, K)
+ *   tile_start  device int32[ntiles + 1]: plan-order offset of each tile
+ * Any pointer may be NULL. */
+riop_status riop_plan_layout(const riop_plan *plan, int32_t *perm, uint32_t *cell,
+                             int32_t *tile_start, void *stream);
+
+/* y = Phi x  (Sec. 5, eq. opmodel, B = I).
+ *   x  device, n*n complex;  y  device, M complex (caller order).  x, y must not alias. */
+riop_status riop_phi(riop_plan *plan, const void *x, void *y, void *stream);
+
+/* x = Phi^dagger y, the exact adjoint of riop_phi (up to rounding).
+ *   y  device, M complex (caller order);  x  device, n*n complex. */
+riop_status riop_phi_adj(riop_plan *plan, const void *y, void *x, void *stream);
+
+/* Plan-order variants of riop_phi / riop_phi_adj: y is indexed by plan order
+ * (see riop_plan_layout), which avoids the scatter/gather through perm. */
+riop_status riop_phi_sorted(riop_plan *plan, const void *x, void *y, void *stream);
+riop_status riop_phi_adj_sorted(riop_plan *plan, const void *y, void *x, void *stream);
+
+/* out = Q x = Phi^dagger Phi x + 2 x, the x-update matrix of Sec. 4.4 for a
+ * Parseval Psi.  x, out device n*n complex; must not alias. */
+riop_status riop_apply_q(riop_plan *plan, const void *x, void *out, void *stream);
+
+/* alpha = Psi^dagger x (Sec. 3.3).  x device n*n complex; alpha device q*n*n complex. */
+riop_status riop_psi_adj(riop_plan *plan, const void *x, void *alpha, void *stream);
+
+/* x = Psi alpha.  alpha device q*n*n complex; x device n*n complex. */
+riop_status riop_psi(riop_plan *plan, const void *alpha, void *x, void *stream);
+
+/* Conjugate gradient for Q x = b (Sec. 4.4, step 5 of Algorithm 1), Hestenes-
+ * Stiefel with complex inner product <a, b> = sum conj(a) b, fixed n_iter
+ * iterations (an exactly zero residual stops early).  Scalars alpha, beta and
+ * all inner products are double precision on the device.
+ *   b       device n*n complex
+ *   x       device n*n complex: initial guess in, solution out
+ *   rr_out  host, nullable: final <r, r> (the call then synchronises) */
+riop_status riop_cg(riop_plan *plan, const void *b, void *x, int32_t n_iter,
+                    double *rr_out, void *stream);
+
+/* gamma = beta * ||Psi^dagger Phi^dagger y||_inf (Sec. 4.4).  Synchronises.
+ *   y  device M complex (caller order);  gamma host. */
+riop_status riop_gamma(riop_plan *plan, const void *y, double beta, double *gamma,
+                       void *stream);
+
+/* SDMM parameters (Algorithm 1 with S = 3, L1 = Psi^dagger, L2 = Phi, L3 = I). */
+typedef struct {
+    int32_t T;            /* SDMM iterations (upper bound when early_stop) */
+    int32_t n_cg;         /* CG iterations per x-update */
+    double gamma;         /* penalty; <= 0 selects beta * ||Psi^dagger Phi^dagger y||_inf */
+    double beta;          /* used when gamma <= 0 (paper: 1e-3) */
+    double xi;            /* halting bound on the relative change of f1 (paper: 1e-3) */
+    double tau;           /* halting tolerance on ||y - Phi x||/eps (paper: 0.1) */
+    int32_t early_stop;   /* 0: run T iterations; 1: stop when the halting rule holds
+                             (checked on the host after every iteration) */
+    int32_t resume;       /* 0: start from Algorithm 1 steps 1-3 with x^(0) = x_inout
+                             (or 0 if x_inout is NULL); 1: continue from the state in
+                             x_inout, z1, z2, z3, rhs and f1_prev */
+    double f1_prev;       /* resume only: f1 of the previous iterate */
+    const void *weights;  /* nullable device, q*n*n reals: diagonal of W in the
+                             coefficient layout; NULL means W = I */
+    void *z1;             /* nullable device q*n*n complex: dual variable of L1 (in/out) */
+    void *z2;             /* nullable device M complex, caller order: dual of L2 (in/out) */
+    void *z3;             /* nullable device n*n complex: dual of L3 (in/out) */
+    void *rhs;            /* nullable device n*n complex: sum_i x_i (in/out) */
+    double *history;      /* nullable host, 4*T doubles: per iteration f1, zeta, nu,
+                             final CG <r, r> */
+} riop_sdmm_params;
+
+typedef struct {
+    int32_t iters;        /* iterations run */
+    double gamma;         /* penalty used */
+    double f1;            /* f1(Psi^dagger x) at the last iterate */
+    double zeta;          /* relative change of f1 (+inf while the previous f1 is 0) */
+    double nu;            /* ||y - Phi x|| / eps */
+} riop_sdmm_stats;
+
+/* Run SDMM (Algorithm 1).  Everything runs on `stream` with no host round trip
+ * inside an iteration unless early_stop is set; the call synchronises once at
+ * the end to fill `stats` and `history`.
+ *   y        device M complex (caller order)
+ *   eps      l2 bound of the data term (> 0)
+ *   x_inout  device n*n complex, nullable unless resume: x^(0) in, x^(T) out
+ *            (if NULL the final iterate is not returned)
+ *   stats    host, nullable
+ * The printed l2-ball projection (eq. prox2) is read as the projection onto the
+ * ball of radius eps centred at y (the set B of Sec. 4.3). */
+riop_status riop_sdmm(riop_plan *plan, const void *y, double eps,
+                      const riop_sdmm_params *params, void *x_inout,
+                      riop_sdmm_stats *stats, void *stream);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *riop_last_error(void);
+
+/* Library version, e.g. "riop 0.1.0 gfx950". */
+const char *riop_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIOP_H */

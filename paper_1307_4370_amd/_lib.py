@@ -1,0 +1,266 @@
+"""ctypes binding of libriop.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts torch
+tensors to device pointers, allocates outputs and turns status codes into
+exceptions.  There is no fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libriop.so")
+
+RIOP_F32 = 1
+RIOP_F64 = 2
+FULL_MASK = (1 << 9) - 1
+
+STATUS = {0: "RIOP_OK", -1: "RIOP_EINVAL", -2: "RIOP_ESHAPE", -3: "RIOP_ENOMEM",
+          -4: "RIOP_EDEVICE", -5: "RIOP_ENOTSUP", -6: "RIOP_ENONFINITE"}
+
+# Entry points declared in include/riop.h (checked by the ABI test).
+EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan_layout",
+           "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
+           "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_gamma",
+           "riop_sdmm", "riop_last_error", "riop_version")
+
+
+class RiopError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("oversample", ctypes.c_int32), ("M", ctypes.c_int64),
+                ("J", ctypes.c_int32), ("levels", ctypes.c_int32), ("dict_mask", ctypes.c_uint32),
+                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("K", ctypes.c_int32), ("J", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("q", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("M", ctypes.c_int64), ("tile", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("nunits", ctypes.c_int32), ("kernel_degree", ctypes.c_int32),
+                ("kb_beta", ctypes.c_double), ("kernel_fit_err", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class SdmmParams(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("n_cg", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("beta", ctypes.c_double), ("xi", ctypes.c_double), ("tau", ctypes.c_double),
+                ("early_stop", ctypes.c_int32), ("resume", ctypes.c_int32),
+                ("f1_prev", ctypes.c_double), ("weights", ctypes.c_void_p),
+                ("z1", ctypes.c_void_p), ("z2", ctypes.c_void_p), ("z3", ctypes.c_void_p),
+                ("rhs", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+class SdmmStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("gamma", ctypes.c_double), ("f1", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libriop.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with paper_1307_4370_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.riop_plan_create.argtypes = [ctypes.POINTER(Desc), vp, vp, ctypes.POINTER(vp)]
+        L.riop_plan_destroy.argtypes = [vp]
+        L.riop_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.riop_plan_layout.argtypes = [vp, vp, vp, vp, vp]
+        for name in ("riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
+                     "riop_apply_q", "riop_psi_adj", "riop_psi"):
+            getattr(L, name).argtypes = [vp, vp, vp, vp]
+        L.riop_cg.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
+        L.riop_gamma.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), vp]
+        L.riop_sdmm.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp,
+                                ctypes.POINTER(SdmmStats), vp]
+        for name in EXPORTS:
+            if name not in ("riop_last_error", "riop_version"):
+                getattr(L, name).restype = ctypes.c_int
+        L.riop_last_error.restype = ctypes.c_char_p
+        L.riop_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise RiopError(status, lib().riop_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class Plan:
+    """One coverage: Phi, Phi^dagger, Psi, Psi^dagger, CG and SDMM on the GPU.
+
+    uv: (M, 2) real tensor on the GPU (float32 for prec='f32', float64 for 'f64'),
+    continuous (u, v) in radians per pixel in [-pi, pi].
+    """
+
+    def __init__(self, n: int, uv: torch.Tensor, J: int = 8, levels: int = 4,
+                 dict_mask: int = FULL_MASK, prec: str = "f32", tile: int = 0, stream=None):
+        self.prec = prec
+        self.rdtype = torch.float32 if prec == "f32" else torch.float64
+        self.cdtype = torch.complex64 if prec == "f32" else torch.complex128
+        if uv.dtype != self.rdtype or not uv.is_cuda or uv.dim() != 2 or uv.shape[1] != 2:
+            raise ValueError(f"uv must be a (M, 2) {self.rdtype} CUDA tensor")
+        uv = uv.contiguous()
+        self.device = uv.device
+        self.n, self.M, self.J, self.levels = n, uv.shape[0], J, levels
+        self.q = bin(dict_mask).count("1")
+        d = Desc(n=n, oversample=2, M=self.M, J=J, levels=levels, dict_mask=dict_mask,
+                 prec=RIOP_F32 if prec == "f32" else RIOP_F64, tile=tile)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().riop_plan_create(ctypes.byref(d), uv.data_ptr(), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._uv = uv
+
+    # -- helpers -----------------------------------------------------------------
+    def _c(self, t: torch.Tensor, shape, name: str) -> torch.Tensor:
+        if t.dtype != self.cdtype or t.device != self.device or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must be a {self.cdtype} tensor of shape {tuple(shape)} on {self.device}")
+        return t.contiguous()
+
+    def _new(self, shape):
+        return torch.empty(shape, dtype=self.cdtype, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().riop_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().riop_plan_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def layout(self, stream=None):
+        inf = self.info()
+        perm = torch.empty(self.M, dtype=torch.int32, device=self.device)
+        cell = torch.empty(self.M, dtype=torch.int32, device=self.device)
+        ts = torch.empty(inf["ntiles"] + 1, dtype=torch.int32, device=self.device)
+        _check(lib().riop_plan_layout(self._h, perm.data_ptr(), cell.data_ptr(), ts.data_ptr(), _stream(stream)))
+        return perm, cell, ts
+
+    # -- operators ---------------------------------------------------------------
+    def phi(self, x, y=None, sorted: bool = False, stream=None):
+        x = self._c(x, (self.n, self.n), "x")
+        y = self._new(self.M) if y is None else y
+        fn = lib().riop_phi_sorted if sorted else lib().riop_phi
+        _check(fn(self._h, x.data_ptr(), y.data_ptr(), _stream(stream)))
+        return y
+
+    def phi_adj(self, y, x=None, sorted: bool = False, stream=None):
+        y = self._c(y, (self.M,), "y")
+        x = self._new((self.n, self.n)) if x is None else x
+        fn = lib().riop_phi_adj_sorted if sorted else lib().riop_phi_adj
+        _check(fn(self._h, y.data_ptr(), x.data_ptr(), _stream(stream)))
+        return x
+
+    def apply_q(self, x, out=None, stream=None):
+        x = self._c(x, (self.n, self.n), "x")
+        out = self._new((self.n, self.n)) if out is None else out
+        _check(lib().riop_apply_q(self._h, x.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def psi_adj(self, x, alpha=None, stream=None):
+        x = self._c(x, (self.n, self.n), "x")
+        alpha = self._new((self.q, self.n, self.n)) if alpha is None else alpha
+        _check(lib().riop_psi_adj(self._h, x.data_ptr(), alpha.data_ptr(), _stream(stream)))
+        return alpha
+
+    def psi(self, alpha, x=None, stream=None):
+        alpha = self._c(alpha, (self.q, self.n, self.n), "alpha")
+        x = self._new((self.n, self.n)) if x is None else x
+        _check(lib().riop_psi(self._h, alpha.data_ptr(), x.data_ptr(), _stream(stream)))
+        return x
+
+    def cg(self, b, x0=None, n_iter: int = 16, stream=None):
+        """Solve Q x = b with n_iter CG iterations; returns (x, final <r, r>)."""
+        b = self._c(b, (self.n, self.n), "b")
+        x = torch.zeros_like(b) if x0 is None else self._c(x0, (self.n, self.n), "x0").clone()
+        rr = ctypes.c_double()
+        _check(lib().riop_cg(self._h, b.data_ptr(), x.data_ptr(), n_iter, ctypes.byref(rr), _stream(stream)))
+        return x, rr.value
+
+    def gamma(self, y, beta: float = 1e-3, stream=None) -> float:
+        y = self._c(y, (self.M,), "y")
+        g = ctypes.c_double()
+        _check(lib().riop_gamma(self._h, y.data_ptr(), beta, ctypes.byref(g), _stream(stream)))
+        return g.value
+
+    def sdmm(self, y, eps: float, T: int, n_cg: int = 16, gamma: float = 0.0, beta: float = 1e-3,
+             x0=None, weights=None, state: dict | None = None, early_stop: bool = False,
+             xi: float = 1e-3, tau: float = 0.1, stream=None):
+        """Run Algorithm 1.  Returns (x, stats, history, state).
+
+        ``state`` (optional) is a dict with z1, z2, z3, rhs tensors and f1_prev;
+        passing one returned by an earlier call resumes that run.
+        """
+        y = self._c(y, (self.M,), "y")
+        n, q = self.n, self.q
+        resume = state is not None
+        if state is None:
+            state = {"z1": self._new((q, n, n)), "z2": self._new(self.M), "z3": self._new((n, n)),
+                     "rhs": self._new((n, n)), "f1_prev": 0.0}
+        if x0 is not None:
+            x = self._c(x0, (n, n), "x0").clone()
+        elif resume:
+            raise ValueError("resuming needs x0 (the previous iterate)")
+        else:
+            x = None
+        w = None
+        if weights is not None:
+            if weights.dtype != self.rdtype or tuple(weights.shape) != (q, n, n):
+                raise ValueError("weights must be a real tensor of shape (q, n, n)")
+            w = weights.contiguous()
+        hist = (ctypes.c_double * (4 * max(1, T)))()
+        prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=xi, tau=tau,
+                         early_stop=int(early_stop), resume=int(resume), f1_prev=state["f1_prev"],
+                         weights=_ptr(w), z1=state["z1"].data_ptr(), z2=state["z2"].data_ptr(),
+                         z3=state["z3"].data_ptr(), rhs=state["rhs"].data_ptr(), history=hist)
+        st = SdmmStats()
+        if x is None:
+            x = torch.zeros((n, n), dtype=self.cdtype, device=self.device)
+        _check(lib().riop_sdmm(self._h, y.data_ptr(), float(eps), ctypes.byref(prm), x.data_ptr(),
+                               ctypes.byref(st), _stream(stream)))
+        history = [tuple(hist[4 * t:4 * t + 4]) for t in range(st.iters)]
+        state["f1_prev"] = st.f1 if st.iters else state["f1_prev"]
+        stats = {k: getattr(st, k) for k, _ in SdmmStats._fields_}
+        return x, stats, history, state
+
+
+def noise_bound(M: int, sigma: float) -> float:
+    """eps^2 = (2M + 4 sqrt(M)) sigma^2 / 2: the chi^2 bound on ||n|| (Sec. 6)."""
+    return math.sqrt((2.0 * M + 4.0 * math.sqrt(M)) * sigma * sigma / 2.0)
+
+
+def version() -> str:
+    return lib().riop_version().decode()

@@ -1,0 +1,195 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/riop.h"
+
+namespace riop {
+
+// ---------------------------------------------------------------------------
+// Complex values: interleaved (re, im) of the plan's real type.
+template <typename R> struct cplx_t;
+template <> struct cplx_t<float> { using type = float2; };
+template <> struct cplx_t<double> { using type = double2; };
+template <typename R> using C = typename cplx_t<R>::type;
+
+template <typename R> __host__ __device__ inline C<R> mk(R re, R im) {
+    C<R> z;
+    z.x = re;
+    z.y = im;
+    return z;
+}
+template <typename R> __device__ inline C<R> cadd(C<R> a, C<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R> __device__ inline C<R> csub(C<R> a, C<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <typename R> __device__ inline C<R> cmul(C<R> a, C<R> b) {
+    return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R> __device__ inline C<R> cscale(C<R> a, R s) { return mk<R>(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------------------
+// Error handling: every entry point converts failures into a riop_status and a
+// thread-local message.
+void set_error(const char *fmt, ...);
+void clear_error();
+
+struct Error {
+    riop_status status;
+    std::string msg;
+};
+
+#define RIOP_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            throw ::riop::Error{e_ == hipErrorOutOfMemory ? RIOP_ENOMEM : RIOP_EDEVICE,        \
+                                std::string(#call) + ": " + hipGetErrorString(e_)};           \
+        }                                                                                     \
+    } while (0)
+
+#define RIOP_REQUIRE(cond, status, msg)                                                       \
+    do {                                                                                      \
+        if (!(cond)) throw ::riop::Error{status, msg};                                        \
+    } while (0)
+
+// Device allocation owned by a plan.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) b = 256;
+        RIOP_HIP(hipMalloc(&ptr, b));
+        bytes = b;
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// One gridding work unit: a tile and a contiguous chunk of its visibilities.
+struct WorkUnit {
+    int32_t tile;
+    int32_t start;  // plan-order index of the first visibility
+    int32_t count;
+    int32_t pad;
+};
+
+constexpr int kMaxStages = 10;
+constexpr int kMaxPoly = 24;  // coefficients per even/odd part
+
+// FFT plan for one transform length.
+struct FftPlan {
+    int N = 0;
+    int E = 0;              // elements per thread
+    int nstages = 0;
+    int radix[kMaxStages] = {};
+    DevBuf twiddle;         // N complex: exp(-2 pi i m / N)
+};
+
+// Device-side SDMM workspace (allocated on first use).
+struct SdmmWork {
+    bool ready = false;
+    DevBuf xhat, rhs, r, p, qp, tmpN, x1, z3loc;
+    DevBuf z1loc, w1;       // q*N complex
+    DevBuf ysort, z2loc, s2; // M complex, plan order
+    DevBuf partials;        // doubles for block reductions
+    DevBuf scalars;         // doubles: scalar slots
+    DevBuf history;         // doubles, 4 per iteration
+};
+
+}  // namespace riop
+
+struct riop_plan {
+    riop_desc desc{};
+    int device = 0;
+    int n = 0, K = 0, J = 0, L = 0, q = 0, prec = 0;
+    int64_t M = 0;
+    uint32_t mask = 0;
+    int bases[9] = {};
+    double scale_q = 1.0;  // 1/sqrt(q)
+
+    // Visibility layout (plan order).
+    int tile = 0, tiles_per_side = 0, ntiles = 0;
+    riop::DevBuf perm;        // int32[M]
+    riop::DevBuf cell;        // uint32[M]: a0 | b0 << 16
+    riop::DevBuf frac;        // R[2M]: (rho_u, rho_v)
+    riop::DevBuf tile_start;  // int32[ntiles + 1]
+    riop::DevBuf units;       // WorkUnit[nunits]
+    int nunits = 0;
+    int max_unit = 0;
+
+    // Kaiser-Bessel kernel: per tap pair even/odd polynomial coefficients.
+    double kb_beta = 0;
+    int kdeg = 0;                // degree of the per-tap polynomial in s
+    int n_even = 0, n_odd = 0;   // coefficients in the even / odd parts
+    double kfit_err = 0;
+    riop::DevBuf kcoef;          // R[J/2][2][kMaxPoly]
+    std::vector<double> kcoef_host;  // same table on the host, double
+    riop::DevBuf deapod;         // R[n]: d(p - n/2)
+
+    // FFT.
+    riop::FftPlan fft;
+
+    // Workspaces.
+    riop::DevBuf tmp;    // K x n complex
+    riop::DevBuf grid;   // K x K complex
+    riop::DevBuf vis;    // M complex, plan order scratch
+    riop::DevBuf img;    // n x n complex scratch
+
+    // SARA.
+    riop::DevBuf filters;   // R[9][16] low-pass filters (index = basis)
+    int flen[9] = {};
+    riop::DevBuf ll;        // per-basis low-low scratch (analysis / synthesis)
+    size_t ll_stride = 0;   // complex entries per basis in `ll`
+
+    riop::SdmmWork sd;
+    int64_t device_bytes = 0;
+};
+
+namespace riop {
+
+inline size_t cbytes(const riop_plan *p) { return p->prec == RIOP_F64 ? 16 : 8; }
+inline size_t rbytes(const riop_plan *p) { return p->prec == RIOP_F64 ? 8 : 4; }
+
+// Launch helpers implemented in the kernel translation units.  All take the
+// plan's real type as a template parameter and enqueue on `st`.
+template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st);
+template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st);
+template <typename R>
+void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st);
+template <typename R>
+void launch_grid(riop_plan *p, const void *y, int order_user, hipStream_t st);
+template <typename R> void launch_fill_zero(void *buf, size_t ncomplex, hipStream_t st);
+template <typename R> void launch_psi_adj(riop_plan *p, const void *x, void *alpha, hipStream_t st);
+template <typename R> void launch_psi(riop_plan *p, const void *alpha, void *x, hipStream_t st);
+
+// SDMM l1 step fused into the last analysis pass (Algorithm 1, steps 7-9, i = 1).
+template <typename R> struct Prox1 {
+    C<R> *z1;          // dual variable, updated in place
+    C<R> *w1;          // r1 - z1 (new), input of the synthesis
+    const R *weights;  // diagonal of W, nullable (W = I)
+    const double *gamma;
+    double *f1_acc;    // accumulates f1 = sum w |Psi^dagger x|
+};
+template <typename R>
+void launch_psi_adj_prox(riop_plan *p, const void *x, const Prox1<R> &px, hipStream_t st);
+
+void build_fft_plan(riop_plan *p, hipStream_t st);
+void build_layout(riop_plan *p, const void *uv, hipStream_t st);
+void build_kernel_tables(riop_plan *p);
+void build_filters(riop_plan *p);
+
+}  // namespace riop

@@ -1,0 +1,388 @@
+// Oversampled unitary 2-D DFT F of the measurement operator (Sec. 5) on the
+// K x K grid, K = 2n, with the zero padding Z and gridding correction D folded
+// into its first pass and their transposes into the last pass of the adjoint.
+//
+// Each pass is a batch of 1-D length-K transforms done by one kernel:
+// Stockham auto-sort, mixed radix (2, 3, 4, 8), data in registers within a
+// stage and exchanged through LDS between stages.  A thread owns the E
+// elements jt + e K/E (e = 0..E-1) of its transform at the start and end of
+// every stage, so global loads and stores are strided by K/E and coalesce.
+//
+// Pruning: the forward transforms read only the n nonzero inputs of the padded
+// line, the adjoint transforms write only the n outputs that survive the crop.
+//
+// Passes (grid stored row-major [k1][k2], k1 <-> u, k2 <-> v):
+//   Phi      : columns of x (n transforms, strided)  -> tmp [K][n]
+//              rows of tmp   (K transforms, contiguous) -> grid [K][K]
+//   Phi^dag  : rows of grid  (K transforms, keep n outputs) -> tmp [K][n]
+//              columns of tmp (n transforms, keep n outputs) -> x
+#include "common.hpp"
+
+namespace riop {
+
+template <typename R> struct FftArgs {
+    const C<R> *in;
+    C<R> *out;
+    const C<R> *tw;      // N twiddles exp(-2 pi i m / N)
+    const R *dax;        // factor along the transform axis (n entries), nullable
+    const R *dbt;        // factor along the batch axis (nbatch entries), nullable
+    long in_ts, in_es;   // strides (in complex elements) between transforms / elements
+    long out_ts, out_es;
+    int N, nbatch, C, n;
+    int pad_in, crop_out;
+    int factors_at_input;
+    int nstages;
+    int radix[kMaxStages];
+    R scale;
+};
+
+// y_r = sum_s x_s w^(r s), w = exp(SGN 2 pi i / RR)
+template <typename R, int RR, int SGN> struct Dft;
+
+template <typename R, int SGN> struct Dft<R, 2, SGN> {
+    __device__ static void run(C<R> *x) {
+        C<R> a = x[0], b = x[1];
+        x[0] = cadd<R>(a, b);
+        x[1] = csub<R>(a, b);
+    }
+};
+
+// multiply by SGN * i
+template <typename R, int SGN> __device__ inline C<R> mul_si(C<R> a) {
+    return SGN > 0 ? mk<R>(-a.y, a.x) : mk<R>(a.y, -a.x);
+}
+
+template <typename R, int SGN> struct Dft<R, 4, SGN> {
+    __device__ static void run(C<R> *x) {
+        C<R> a = cadd<R>(x[0], x[2]), b = csub<R>(x[0], x[2]);
+        C<R> c = cadd<R>(x[1], x[3]), d = mul_si<R, SGN>(csub<R>(x[1], x[3]));
+        x[0] = cadd<R>(a, c);
+        x[2] = csub<R>(a, c);
+        x[1] = cadd<R>(b, d);
+        x[3] = csub<R>(b, d);
+    }
+};
+
+template <typename R, int SGN> struct Dft<R, 8, SGN> {
+    __device__ static void run(C<R> *x) {
+        C<R> e[4] = {x[0], x[2], x[4], x[6]};
+        C<R> o[4] = {x[1], x[3], x[5], x[7]};
+        Dft<R, 4, SGN>::run(e);
+        Dft<R, 4, SGN>::run(o);
+        const R h = R(0.70710678118654752440084436210484903928);
+        // w8^1 = (1 + SGN i)/sqrt2, w8^2 = SGN i, w8^3 = (-1 + SGN i)/sqrt2
+        C<R> t1 = mk<R>(h * (o[1].x - SGN * o[1].y), h * (o[1].y + SGN * o[1].x));
+        C<R> t2 = mul_si<R, SGN>(o[2]);
+        C<R> t3 = mk<R>(h * (-o[3].x - SGN * o[3].y), h * (-o[3].y + SGN * o[3].x));
+        x[0] = cadd<R>(e[0], o[0]);
+        x[4] = csub<R>(e[0], o[0]);
+        x[1] = cadd<R>(e[1], t1);
+        x[5] = csub<R>(e[1], t1);
+        x[2] = cadd<R>(e[2], t2);
+        x[6] = csub<R>(e[2], t2);
+        x[3] = cadd<R>(e[3], t3);
+        x[7] = csub<R>(e[3], t3);
+    }
+};
+
+template <typename R, int SGN> struct Dft<R, 3, SGN> {
+    __device__ static void run(C<R> *x) {
+        const R s3 = R(0.86602540378443864676372317075293618347);
+        C<R> t = cadd<R>(x[1], x[2]);
+        C<R> u = csub<R>(x[1], x[2]);
+        C<R> m = mk<R>(x[0].x - R(0.5) * t.x, x[0].y - R(0.5) * t.y);
+        C<R> v = mul_si<R, SGN>(cscale<R>(u, s3));
+        x[0] = cadd<R>(x[0], t);
+        x[1] = cadd<R>(m, v);
+        x[2] = csub<R>(m, v);
+    }
+};
+
+// One Stockham stage of radix RR on the thread's E registers.
+template <typename R, int E, int RR, int SGN>
+__device__ inline void stage(C<R> (&v)[E], int jt, int NE, int N, int Ns, const C<R> *tw) {
+    constexpr int B = E / RR;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = jt + b * NE;
+        const int k = j % Ns;
+        C<R> x[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) x[r] = v[b + r * B];
+        if (Ns > 1) {
+            const int step = N / (Ns * RR);
+#pragma unroll
+            for (int r = 1; r < RR; ++r) {
+                C<R> w = tw[r * k * step];
+                if (SGN > 0) w.y = -w.y;
+                x[r] = cmul<R>(x[r], w);
+            }
+        }
+        Dft<R, RR, SGN>::run(x);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) v[b + r * B] = x[r];
+    }
+}
+
+template <typename R, int E>
+__device__ inline void exchange(C<R> (&v)[E], C<R> *lds, int ls, int jt, int NE, int Ns, int RR) {
+    // v[b + r*B] holds output r of butterfly j = jt + b*NE, destined for
+    // position (j - k) * RR + k + r * Ns with k = j mod Ns.
+    const int B = E / RR;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int b = e % B, r = e / B;
+        const int j = jt + b * NE;
+        const int k = j % Ns;
+        lds[((j - k) * RR + k + r * Ns) * ls] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = lds[(jt + e * NE) * ls];
+}
+
+// Map line index i of a padded length-N line to its source index in [0, n),
+// or -1 inside the zero band: pixel j sits at line index (j - n/2) mod N.
+__device__ inline int band_index(int i, int N, int n) {
+    const int h = n >> 1;
+    if (i < h) return i + h;
+    if (i >= N - h) return i - (N - h);
+    return -1;
+}
+
+template <typename R, int E, int SGN, bool COLS>
+__global__ void __launch_bounds__(1024) fft_pass(FftArgs<R> a) {
+    extern __shared__ unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+    const int N = a.N;
+    const int NE = N / E;
+    int c, jt;
+    if (COLS) {
+        c = threadIdx.x % a.C;
+        jt = threadIdx.x / a.C;
+    } else {
+        c = threadIdx.x / NE;
+        jt = threadIdx.x % NE;
+    }
+    // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // range of transforms so neighbouring columns share its L2.
+    int blk = blockIdx.x;
+    if (COLS) {
+        const int nb = gridDim.x, qq = nb >> 3, rr = nb & 7, x = blk & 7;
+        blk = x * qq + min(x, rr) + (blk >> 3);
+    }
+    const long t = (long)blk * a.C + c;
+    const bool active = t < a.nbatch;
+    C<R> *lds = COLS ? smem + c : smem + (long)c * N;
+    const int ls = COLS ? a.C : 1;
+
+    C<R> v[E];
+    const R tf = (active && a.dbt && a.factors_at_input) ? a.dbt[t] : R(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = jt + e * NE;
+        const int j = a.pad_in ? band_index(i, N, a.n) : i;
+        C<R> z = mk<R>(0, 0);
+        if (active && j >= 0) {
+            z = a.in[t * a.in_ts + (long)j * a.in_es];
+            if (a.factors_at_input) {
+                R f = a.scale * tf;
+                if (a.dax) f *= a.dax[j];
+                z = cscale<R>(z, f);
+            }
+        }
+        v[e] = z;
+    }
+
+    int Ns = 1;
+    for (int s = 0; s < a.nstages; ++s) {
+        const int RR = a.radix[s];
+        if (s > 0) exchange<R, E>(v, lds, ls, jt, NE, Ns, a.radix[s - 1]);
+        if (s > 0) Ns *= a.radix[s - 1];
+        switch (RR) {
+            case 8: if constexpr (E % 8 == 0) stage<R, E, 8, SGN>(v, jt, NE, N, Ns, a.tw); break;
+            case 4: if constexpr (E % 4 == 0) stage<R, E, 4, SGN>(v, jt, NE, N, Ns, a.tw); break;
+            case 3: if constexpr (E % 3 == 0) stage<R, E, 3, SGN>(v, jt, NE, N, Ns, a.tw); break;
+            default: if constexpr (E % 2 == 0) stage<R, E, 2, SGN>(v, jt, NE, N, Ns, a.tw); break;
+        }
+    }
+
+    if (!active) return;
+    const R tf_out = (a.dbt && !a.factors_at_input) ? a.dbt[t] : R(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = jt + e * NE;
+        const int j = a.crop_out ? band_index(i, N, a.n) : i;
+        if (j < 0) continue;
+        C<R> z = v[e];
+        if (!a.factors_at_input) {
+            R f = a.scale * tf_out;
+            if (a.dax) f *= a.dax[j];
+            z = cscale<R>(z, f);
+        }
+        a.out[t * a.out_ts + (long)j * a.out_es] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+static int elems_per_thread(const FftPlan &f) { return f.E; }
+
+void build_fft_plan(riop_plan *p, hipStream_t st) {
+    FftPlan &f = p->fft;
+    const int N = p->K;
+    f.N = N;
+    int m = N, threes = 0;
+    while (m % 3 == 0) {
+        m /= 3;
+        ++threes;
+    }
+    RIOP_REQUIRE((m & (m - 1)) == 0 && m >= 8, RIOP_ENOTSUP,
+                 "grid side K = 2n must be 2^a 3^b with 2^a >= 8");
+    f.nstages = 0;
+    int rest = m;
+    while (rest >= 8) {
+        f.radix[f.nstages++] = 8;
+        rest /= 8;
+    }
+    if (rest == 4) f.radix[f.nstages++] = 4;
+    if (rest == 2) f.radix[f.nstages++] = 2;
+    for (int i = 0; i < threes; ++i) f.radix[f.nstages++] = 3;
+    RIOP_REQUIRE(f.nstages <= kMaxStages, RIOP_ENOTSUP, "too many FFT stages");
+    f.E = threes ? 24 : 8;
+    RIOP_REQUIRE(N % f.E == 0, RIOP_ENOTSUP, "grid side not divisible by the FFT thread width");
+
+    // Twiddles exp(-2 pi i m / N) from double-precision sin/cos.
+    const size_t cb = cbytes(p);
+    std::vector<double> tw(2 * (size_t)N);
+    for (int k = 0; k < N; ++k) {
+        // Reduce the angle to [0, pi/4]-ish accuracy by exact symmetries is not
+        // needed: cos/sin of 2 pi k / N in double are accurate to ~1 ulp.
+        const double ang = -2.0 * M_PI * (double)k / (double)N;
+        tw[2 * k] = cos(ang);
+        tw[2 * k + 1] = sin(ang);
+    }
+    f.twiddle.alloc(cb * N);
+    if (p->prec == RIOP_F64) {
+        RIOP_HIP(hipMemcpyAsync(f.twiddle.ptr, tw.data(), cb * N, hipMemcpyHostToDevice, st));
+    } else {
+        std::vector<float> t32(2 * (size_t)N);
+        for (size_t i = 0; i < t32.size(); ++i) t32[i] = (float)tw[i];
+        RIOP_HIP(hipMemcpyAsync(f.twiddle.ptr, t32.data(), cb * N, hipMemcpyHostToDevice, st));
+    }
+    RIOP_HIP(hipStreamSynchronize(st));
+}
+
+template <typename R, int SGN, bool COLS>
+static void launch_pass(riop_plan *p, FftArgs<R> a, hipStream_t st) {
+    const FftPlan &f = p->fft;
+    a.N = f.N;
+    a.nstages = f.nstages;
+    for (int i = 0; i < f.nstages; ++i) a.radix[i] = f.radix[i];
+    a.tw = f.twiddle.as<C<R>>();
+    const int E = elems_per_thread(f);
+    const int NE = f.N / E;
+    const size_t lds_budget = 64 * 1024;
+    const size_t line = sizeof(C<R>) * (size_t)f.N;
+    int Cb;
+    if (COLS) {
+        Cb = (int)std::min<size_t>(lds_budget / line, 1024 / NE);
+        Cb = std::max(1, std::min(Cb, 16));
+    } else {
+        Cb = std::max(1, 256 / NE);
+        Cb = (int)std::max<size_t>(1, std::min<size_t>(Cb, lds_budget / line));
+    }
+    a.C = Cb;
+    const int threads = Cb * NE;
+    RIOP_REQUIRE(threads <= 1024, RIOP_ENOTSUP, "FFT block too large");
+    const int blocks = (a.nbatch + Cb - 1) / Cb;
+    const size_t lds = line * Cb;
+    if (E == 8)
+        hipLaunchKernelGGL((fft_pass<R, 8, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a);
+    else
+        hipLaunchKernelGGL((fft_pass<R, 24, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a);
+    RIOP_HIP(hipGetLastError());
+}
+
+template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st) {
+    const int n = p->n, K = p->K;
+    const R *d = p->deapod.as<R>();
+    // Pass 1: columns q of x, transform over p; pad, correct by d(p) d(q), scale 1/K.
+    FftArgs<R> a{};
+    a.in = static_cast<const C<R> *>(x);
+    a.out = p->tmp.as<C<R>>();
+    a.in_ts = 1;
+    a.in_es = n;
+    a.out_ts = 1;
+    a.out_es = n;
+    a.nbatch = n;
+    a.n = n;
+    a.pad_in = 1;
+    a.crop_out = 0;
+    a.dax = d;
+    a.dbt = d;
+    a.factors_at_input = 1;
+    a.scale = R(1) / R(K);
+    launch_pass<R, -1, true>(p, a, st);
+    // Pass 2: rows k1 of tmp, transform over q (padded) -> grid row k1.
+    FftArgs<R> b{};
+    b.in = p->tmp.as<C<R>>();
+    b.out = p->grid.as<C<R>>();
+    b.in_ts = n;
+    b.in_es = 1;
+    b.out_ts = K;
+    b.out_es = 1;
+    b.nbatch = K;
+    b.n = n;
+    b.pad_in = 1;
+    b.crop_out = 0;
+    b.factors_at_input = 1;
+    b.scale = R(1);
+    launch_pass<R, -1, false>(p, b, st);
+}
+
+template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st) {
+    const int n = p->n, K = p->K;
+    const R *d = p->deapod.as<R>();
+    // Pass 1: rows k1 of grid, inverse transform over k2, keep the n cropped outputs.
+    FftArgs<R> a{};
+    a.in = p->grid.as<C<R>>();
+    a.out = p->tmp.as<C<R>>();
+    a.in_ts = K;
+    a.in_es = 1;
+    a.out_ts = n;
+    a.out_es = 1;
+    a.nbatch = K;
+    a.n = n;
+    a.pad_in = 0;
+    a.crop_out = 1;
+    a.factors_at_input = 0;
+    a.scale = R(1);
+    launch_pass<R, +1, false>(p, a, st);
+    // Pass 2: columns q of tmp, inverse over k1, crop to p, correct by d(p) d(q), 1/K.
+    FftArgs<R> b{};
+    b.in = p->tmp.as<C<R>>();
+    b.out = static_cast<C<R> *>(x);
+    b.in_ts = 1;
+    b.in_es = n;
+    b.out_ts = 1;
+    b.out_es = n;
+    b.nbatch = n;
+    b.n = n;
+    b.pad_in = 0;
+    b.crop_out = 1;
+    b.dax = d;
+    b.dbt = d;
+    b.factors_at_input = 0;
+    b.scale = R(1) / R(K);
+    launch_pass<R, +1, true>(p, b, st);
+}
+
+template void launch_phi_fft_forward<float>(riop_plan *, const void *, hipStream_t);
+template void launch_phi_fft_forward<double>(riop_plan *, const void *, hipStream_t);
+template void launch_phi_fft_adjoint<float>(riop_plan *, void *, hipStream_t);
+template void launch_phi_fft_adjoint<double>(riop_plan *, void *, hipStream_t);
+
+}  // namespace riop

@@ -1,0 +1,566 @@
+// SDMM (Sec. 4.4, Algorithm 1) with S = 3: L1 = Psi^dagger, L2 = Phi, L3 = I,
+// f1 = ||W .||_1, f2 = indicator of the l2 ball of radius eps around y,
+// f3 = indicator of the positive orthant; x-update by conjugate gradient on
+// Q = Phi^dagger Phi + 2 I (Parseval Psi, Sec. 4.4).
+//
+// Everything is enqueued on the caller's stream; inner products, norms and
+// the CG scalars alpha, beta are double precision and stay on the device.
+// Reductions are deterministic: each block writes a partial sum to a slot,
+// and every consumer block adds the slot's partials in the same fixed order.
+// Visibility-length vectors (y, z2, Phi x) are kept in plan order, so Phi and
+// Phi^dagger inside the loop avoid the permutation to the caller's order.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "common.hpp"
+
+namespace riop {
+
+
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// Partial-sum slots (each kRedBlocks doubles).
+enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, kSlots };
+// Scalar slots.
+enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, kScalars };
+
+__device__ inline double block_sum(double v) {
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double block_max(double v) {
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Sum of one slot's partials, in a fixed order, computed by the whole block.
+__device__ inline double slot_sum(const double *partials, int slot) {
+    __shared__ double tot;
+    double v = 0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) v += partials[slot * kRedBlocks + i];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) tot = s;
+    __syncthreads();
+    return tot;
+}
+
+#define GRID_LOOP(i, n) for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
+
+template <typename R> __device__ inline double abs2(C<R> z) { return (double)z.x * z.x + (double)z.y * z.y; }
+
+// r = b - (Qx_partial + 2 x); p = r; slot <- sum |r|^2
+template <typename R>
+__global__ void cg_init(const C<R> *b, const C<R> *x, const C<R> *ax, C<R> *r, C<R> *p, long N, double *partials,
+                        int slot) {
+    double acc = 0;
+    GRID_LOOP(i, N) {
+        const C<R> xi = x[i], ai = ax[i], bi = b[i];
+        const C<R> ri = mk<R>(bi.x - (ai.x + R(2) * xi.x), bi.y - (ai.y + R(2) * xi.y));
+        r[i] = ri;
+        p[i] = ri;
+        acc += abs2<R>(ri);
+    }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
+}
+
+// qp <- qp + 2 p ; slot <- sum Re(conj(p) qp)
+template <typename R> __global__ void cg_pq(const C<R> *p, C<R> *qp, long N, double *partials, int slot) {
+    double acc = 0;
+    GRID_LOOP(i, N) {
+        const C<R> pi = p[i];
+        C<R> q = qp[i];
+        q.x += R(2) * pi.x;
+        q.y += R(2) * pi.y;
+        qp[i] = q;
+        acc += (double)pi.x * q.x + (double)pi.y * q.y;
+    }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
+}
+
+// alpha = rr_old / pq ; x += alpha p ; r -= alpha qp ; slot_new <- sum |r|^2
+template <typename R>
+__global__ void cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long N, double *partials, int slot_old,
+                          int slot_pq, int slot_new) {
+    const double rr = slot_sum(partials, slot_old);
+    const double pq = slot_sum(partials, slot_pq);
+    const double alpha = (rr == 0.0 || pq == 0.0) ? 0.0 : rr / pq;
+    double acc = 0;
+    GRID_LOOP(i, N) {
+        const C<R> pi = p[i], qi = qp[i];
+        C<R> xi = x[i], ri = r[i];
+        xi.x = (R)((double)xi.x + alpha * pi.x);
+        xi.y = (R)((double)xi.y + alpha * pi.y);
+        ri.x = (R)((double)ri.x - alpha * qi.x);
+        ri.y = (R)((double)ri.y - alpha * qi.y);
+        x[i] = xi;
+        r[i] = ri;
+        acc += abs2<R>(ri);
+    }
+    __syncthreads();
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partials[slot_new * kRedBlocks + blockIdx.x] = s;
+}
+
+// beta = rr_new / rr_old ; p = r + beta p
+template <typename R>
+__global__ void cg_direction(const C<R> *r, C<R> *p, long N, const double *partials, int slot_old, int slot_new) {
+    const double rr_old = slot_sum(partials, slot_old);
+    const double rr_new = slot_sum(partials, slot_new);
+    const double beta = rr_old == 0.0 ? 0.0 : rr_new / rr_old;
+    GRID_LOOP(i, N) {
+        const C<R> ri = r[i], pi = p[i];
+        p[i] = mk<R>((R)((double)ri.x + beta * pi.x), (R)((double)ri.y + beta * pi.y));
+    }
+}
+
+// An exactly zero residual stops CG: the update kernels above turn 0/0 into
+// alpha = beta = 0, so the iterate no longer changes.
+
+__global__ void slot_to_scalar(const double *partials, int slot, double *scalars, int which) {
+    const double s = slot_sum(partials, slot);
+    if (threadIdx.x == 0) scalars[which] = s;
+}
+
+// out = a + 2 b
+template <typename R> __global__ void add_2x(const C<R> *a, const C<R> *b, C<R> *out, long N) {
+    GRID_LOOP(i, N) {
+        const C<R> ai = a[i], bi = b[i];
+        out[i] = mk<R>(ai.x + R(2) * bi.x, ai.y + R(2) * bi.y);
+    }
+}
+
+// slot <- max |v|
+template <typename R> __global__ void max_abs(const C<R> *v, long n, double *partials, int slot) {
+    double m = 0;
+    GRID_LOOP(i, n) m = fmax(m, sqrt(abs2<R>(v[i])));
+    const double s = block_max(m);
+    if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
+}
+
+__global__ void gamma_from_max(const double *partials, int slot, double beta, double *scalars) {
+    double m = 0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) m = fmax(m, partials[slot * kRedBlocks + i]);
+    m = block_max(m);
+    if (threadIdx.x == 0) scalars[SC_GAMMA] = beta * m;
+}
+
+__global__ void set_scalar(double *scalars, int which, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) scalars[which] = v;
+}
+
+// Gather / scatter between caller order and plan order.
+template <typename R> __global__ void gather_perm(const C<R> *src, const int *perm, C<R> *dst, long M) {
+    GRID_LOOP(i, M) dst[i] = src[perm[i]];
+}
+template <typename R> __global__ void scatter_perm(const C<R> *src, const int *perm, C<R> *dst, long M) {
+    GRID_LOOP(i, M) dst[perm[i]] = src[i];
+}
+
+// prox2 pass 1: slot_e <- sum |s + z2 - y|^2, slot_nu <- sum |y - s|^2
+template <typename R>
+__global__ void prox2_norms(const C<R> *s, const C<R> *z2, const C<R> *y, long M, double *partials) {
+    double e = 0, nu = 0;
+    GRID_LOOP(i, M) {
+        const C<R> si = s[i], zi = z2[i], yi = y[i];
+        const double dr = (double)si.x + zi.x - yi.x, di = (double)si.y + zi.y - yi.y;
+        e += dr * dr + di * di;
+        const double fr = (double)yi.x - si.x, fi = (double)yi.y - si.y;
+        nu += fr * fr + fi * fi;
+    }
+    const double se = block_sum(e);
+    const double sn = block_sum(nu);
+    if (threadIdx.x == 0) {
+        partials[SLOT_E * kRedBlocks + blockIdx.x] = se;
+        partials[SLOT_NU * kRedBlocks + blockIdx.x] = sn;
+    }
+}
+
+// prox2 pass 2: v = s + z2; r2 = y + (v - y) min(1, eps/||v - y||);
+// z2 <- v - r2; w2 = r2 - z2 (input of Phi^dagger).
+template <typename R>
+__global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, long M, const double *partials,
+                             const double *scalars) {
+    const double e = sqrt(slot_sum(partials, SLOT_E));
+    const double eps = scalars[SC_EPS];
+    const double sc = e > eps ? eps / e : 1.0;
+    GRID_LOOP(i, M) {
+        const C<R> si = s[i], zi = z2[i], yi = y[i];
+        const double vr = (double)si.x + zi.x, vi = (double)si.y + zi.y;
+        const double rr = yi.x + (vr - yi.x) * sc, ri = yi.y + (vi - yi.y) * sc;
+        const double znr = vr - rr, zni = vi - ri;
+        z2[i] = mk<R>((R)znr, (R)zni);
+        w2[i] = mk<R>((R)(rr - znr), (R)(ri - zni));
+    }
+}
+
+// prox3 and the right-hand side: v = xhat + z3; r3 = max(Re v, 0);
+// z3 <- v - r3; rhs = x1 + x2 + (r3 - z3).
+template <typename R>
+__global__ void prox3_rhs(const C<R> *xh, C<R> *z3, const C<R> *x1, const C<R> *x2, C<R> *rhs, long N) {
+    GRID_LOOP(i, N) {
+        const C<R> xi = xh[i], zi = z3[i];
+        const R vr = xi.x + zi.x, vi = xi.y + zi.y;
+        const R r3 = vr > R(0) ? vr : R(0);
+        const C<R> zn = mk<R>(vr - r3, vi);
+        z3[i] = zn;
+        const C<R> a = x1[i], b = x2[i];
+        rhs[i] = mk<R>(a.x + b.x + (r3 - zn.x), a.y + b.y - zn.y);
+    }
+}
+
+// rhs = a + b + c
+template <typename R> __global__ void add3(const C<R> *a, const C<R> *b, const C<R> *c, C<R> *out, long N) {
+    GRID_LOOP(i, N) {
+        const C<R> x = a[i], y = b[i], z = c[i];
+        out[i] = mk<R>(x.x + y.x + z.x, x.y + y.y + z.y);
+    }
+}
+
+// history[t] = {f1, zeta, nu, final CG rr}; f1_prev <- f1
+__global__ void record_stats(const double *partials, double *scalars, double *hist, int t, int rr_slot) {
+    const double nu2 = slot_sum(partials, SLOT_NU);
+    const double rr = slot_sum(partials, rr_slot);
+    if (threadIdx.x == 0) {
+        const double f1 = scalars[SC_F1ACC];
+        const double prev = scalars[SC_F1PREV];
+        const double zeta = prev == 0.0 ? INFINITY : fabs(f1 - prev) / fabs(prev);
+        hist[4 * t + 0] = f1;
+        hist[4 * t + 1] = zeta;
+        hist[4 * t + 2] = sqrt(nu2) / scalars[SC_EPS];
+        hist[4 * t + 3] = rr;
+        scalars[SC_F1PREV] = f1;
+        scalars[SC_RRFINAL] = rr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+static dim3 RB() { return dim3(kRedBlocks); }
+static dim3 RT() { return dim3(kRedThreads); }
+
+static void ensure_work(riop_plan *p) {
+    SdmmWork &w = p->sd;
+    if (w.ready) return;
+    const size_t cb = cbytes(p);
+    const size_t N = (size_t)p->n * p->n, D = (size_t)p->q * N, M = (size_t)std::max<int64_t>(1, p->M);
+    w.xhat.alloc(cb * N);
+    w.rhs.alloc(cb * N);
+    w.r.alloc(cb * N);
+    w.p.alloc(cb * N);
+    w.qp.alloc(cb * N);
+    w.tmpN.alloc(cb * N);
+    w.x1.alloc(cb * N);
+    w.z3loc.alloc(cb * N);
+    w.z1loc.alloc(cb * D);
+    w.w1.alloc(cb * D);
+    w.ysort.alloc(cb * M);
+    w.z2loc.alloc(cb * M);
+    w.s2.alloc(cb * M);
+    w.partials.alloc(sizeof(double) * kSlots * kRedBlocks);
+    w.scalars.alloc(sizeof(double) * kScalars);
+    w.ready = true;
+}
+
+template <typename R> static void gram_sorted(riop_plan *p, const void *x, void *out, hipStream_t s) {
+    // out = Phi^dagger Phi x (plan order inside).
+    launch_phi_fft_forward<R>(p, x, s);
+    launch_degrid<R>(p, p->vis.ptr, 0, s);
+    launch_grid<R>(p, p->vis.ptr, 0, s);
+    launch_phi_fft_adjoint<R>(p, out, s);
+}
+
+template <typename R>
+static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_slot, hipStream_t s) {
+    ensure_work(p);
+    SdmmWork &w = p->sd;
+    const long N = (long)p->n * p->n;
+    double *part = w.partials.as<double>();
+    gram_sorted<R>(p, x, w.qp.ptr, s);
+    hipLaunchKernelGGL(cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
+                       w.qp.as<C<R>>(), w.r.as<C<R>>(), w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
+    RIOP_HIP(hipGetLastError());
+    int cur = SLOT_RR0;
+    for (int k = 0; k < n_iter; ++k) {
+        const int nxt = cur == SLOT_RR0 ? SLOT_RR1 : SLOT_RR0;
+        gram_sorted<R>(p, w.p.ptr, w.qp.ptr, s);
+        hipLaunchKernelGGL(cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
+        hipLaunchKernelGGL(cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r.as<C<R>>(), w.p.as<C<R>>(),
+                           w.qp.as<C<R>>(), N, part, cur, (int)SLOT_PQ, nxt);
+        hipLaunchKernelGGL(cg_direction<R>, RB(), RT(), 0, s, w.r.as<C<R>>(), w.p.as<C<R>>(), N,
+                           (const double *)part, cur, nxt);
+        RIOP_HIP(hipGetLastError());
+        cur = nxt;
+    }
+    *final_slot = cur;
+}
+
+template <typename R> static void gamma_run(riop_plan *p, const void *y_sorted_or_user, int user, double beta,
+                                            hipStream_t s) {
+    ensure_work(p);
+    SdmmWork &w = p->sd;
+    const long D = (long)p->q * p->n * p->n;
+    launch_grid<R>(p, y_sorted_or_user, user, s);
+    launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
+    launch_psi_adj<R>(p, w.tmpN.ptr, w.w1.ptr, s);
+    hipLaunchKernelGGL(max_abs<R>, RB(), RT(), 0, s, w.w1.as<C<R>>(), D, w.partials.as<double>(), (int)SLOT_MAX);
+    hipLaunchKernelGGL(gamma_from_max, dim3(1), RT(), 0, s, (const double *)w.partials.as<double>(), (int)SLOT_MAX,
+                       beta, w.scalars.as<double>());
+    RIOP_HIP(hipGetLastError());
+}
+
+template <typename R>
+static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, void *x_inout,
+                     riop_sdmm_stats *stats, hipStream_t s) {
+    ensure_work(p);
+    SdmmWork &w = p->sd;
+    const long N = (long)p->n * p->n, D = (long)p->q * N, M = (long)p->M;
+    const size_t cb = cbytes(p);
+    double *part = w.partials.as<double>();
+    double *sc = w.scalars.as<double>();
+    const int T = std::max(0, prm->T);
+    w.history.alloc(sizeof(double) * 4 * std::max(1, T));
+    C<R> *xh = w.xhat.as<C<R>>();
+
+    // Visibilities in plan order.
+    if (M > 0)
+        hipLaunchKernelGGL(gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(y), p->perm.as<int>(),
+                           w.ysort.as<C<R>>(), M);
+    hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_EPS, eps);
+    // Penalty.
+    if (prm->gamma > 0) {
+        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_GAMMA, prm->gamma);
+    } else {
+        gamma_run<R>(p, w.ysort.ptr, 0, prm->beta, s);
+    }
+    RIOP_HIP(hipGetLastError());
+
+    if (prm->resume) {
+        RIOP_REQUIRE(x_inout && prm->z1 && prm->z2 && prm->z3 && prm->rhs, RIOP_EINVAL,
+                     "resume needs x_inout, z1, z2, z3 and rhs");
+        RIOP_HIP(hipMemcpyAsync(xh, x_inout, cb * N, hipMemcpyDeviceToDevice, s));
+        RIOP_HIP(hipMemcpyAsync(w.z1loc.ptr, prm->z1, cb * D, hipMemcpyDeviceToDevice, s));
+        RIOP_HIP(hipMemcpyAsync(w.z3loc.ptr, prm->z3, cb * N, hipMemcpyDeviceToDevice, s));
+        RIOP_HIP(hipMemcpyAsync(w.rhs.ptr, prm->rhs, cb * N, hipMemcpyDeviceToDevice, s));
+        if (M > 0)
+            hipLaunchKernelGGL(gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(prm->z2),
+                               p->perm.as<int>(), w.z2loc.as<C<R>>(), M);
+        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, prm->f1_prev);
+    } else {
+        // Algorithm 1 steps 1-3: z_i = 0, r_i = L_i x0, x_i = L_i^dagger r_i.
+        launch_fill_zero<R>(w.z1loc.ptr, D, s);
+        launch_fill_zero<R>(w.z2loc.ptr, std::max<long>(1, M), s);
+        launch_fill_zero<R>(w.z3loc.ptr, N, s);
+        if (x_inout) {
+            RIOP_HIP(hipMemcpyAsync(xh, x_inout, cb * N, hipMemcpyDeviceToDevice, s));
+            launch_psi_adj<R>(p, xh, w.w1.ptr, s);
+            launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+            gram_sorted<R>(p, xh, w.tmpN.ptr, s);
+            hipLaunchKernelGGL(add3<R>, RB(), RT(), 0, s, w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), (const C<R> *)xh,
+                               w.rhs.as<C<R>>(), N);
+        } else {
+            launch_fill_zero<R>(xh, N, s);
+            launch_fill_zero<R>(w.rhs.ptr, N, s);
+        }
+        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, 0.0);
+    }
+    RIOP_HIP(hipGetLastError());
+
+    Prox1<R> px{w.z1loc.as<C<R>>(), w.w1.as<C<R>>(), static_cast<const R *>(prm->weights), sc + SC_GAMMA,
+                sc + SC_F1ACC};
+    std::vector<double> hist(4 * std::max(1, T), 0.0);
+    int iters = 0;
+    for (int t = 0; t < T; ++t) {
+        // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x.
+        int rr_slot = SLOT_RR0;
+        cg_run<R>(p, w.rhs.ptr, xh, prm->n_cg, &rr_slot, s);
+        // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
+        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1ACC, 0.0);
+        launch_psi_adj_prox<R>(p, xh, px, s);
+        launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+        // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2).
+        launch_phi_fft_forward<R>(p, xh, s);
+        launch_degrid<R>(p, w.s2.ptr, 0, s);
+        if (M > 0) {
+            hipLaunchKernelGGL(prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
+                               w.ysort.as<C<R>>(), M, part);
+            hipLaunchKernelGGL(prox2_update<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
+                               w.ysort.as<C<R>>(), p->vis.as<C<R>>(), M, (const double *)part,
+                               (const double *)sc);
+        } else {
+            hipLaunchKernelGGL(prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
+                               w.ysort.as<C<R>>(), 0L, part);
+        }
+        launch_grid<R>(p, p->vis.ptr, 0, s);
+        launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
+        // i = 3 and the next right-hand side.
+        hipLaunchKernelGGL(prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(),
+                           w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), w.rhs.as<C<R>>(), N);
+        hipLaunchKernelGGL(record_stats, dim3(1), RT(), 0, s, (const double *)part, sc, w.history.as<double>(), t,
+                           rr_slot);
+        RIOP_HIP(hipGetLastError());
+        iters = t + 1;
+        if (prm->early_stop) {
+            RIOP_HIP(hipMemcpyAsync(&hist[4 * t], w.history.as<double>() + 4 * t, 4 * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+            RIOP_HIP(hipStreamSynchronize(s));
+            if (!std::isfinite(hist[4 * t + 2]))
+                throw Error{RIOP_ENONFINITE, "non-finite residual norm in SDMM"};
+            const double zeta = hist[4 * t + 1], nu = hist[4 * t + 2];
+            if (zeta < prm->xi && nu >= 1.0 - prm->tau && nu <= 1.0 + prm->tau) break;
+        }
+    }
+    // Results.
+    if (x_inout) RIOP_HIP(hipMemcpyAsync(x_inout, xh, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm->z1) RIOP_HIP(hipMemcpyAsync(prm->z1, w.z1loc.ptr, cb * D, hipMemcpyDeviceToDevice, s));
+    if (prm->z3) RIOP_HIP(hipMemcpyAsync(prm->z3, w.z3loc.ptr, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm->rhs) RIOP_HIP(hipMemcpyAsync(prm->rhs, w.rhs.ptr, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm->z2 && M > 0)
+        hipLaunchKernelGGL(scatter_perm<R>, RB(), RT(), 0, s, (const C<R> *)w.z2loc.as<C<R>>(), p->perm.as<int>(),
+                           static_cast<C<R> *>(prm->z2), M);
+    double scal[kScalars] = {};
+    RIOP_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, s));
+    if (iters > 0)
+        RIOP_HIP(hipMemcpyAsync(hist.data(), w.history.ptr, sizeof(double) * 4 * iters, hipMemcpyDeviceToHost, s));
+    RIOP_HIP(hipStreamSynchronize(s));
+    if (prm->history) std::copy(hist.begin(), hist.begin() + 4 * iters, prm->history);
+    if (stats) {
+        stats->iters = iters;
+        stats->gamma = scal[SC_GAMMA];
+        stats->f1 = iters ? hist[4 * (iters - 1)] : 0.0;
+        stats->zeta = iters ? hist[4 * (iters - 1) + 1] : INFINITY;
+        stats->nu = iters ? hist[4 * (iters - 1) + 2] : 0.0;
+    }
+    for (int t = 0; t < iters; ++t)
+        if (!std::isfinite(hist[4 * t]) || !std::isfinite(hist[4 * t + 2]))
+            throw Error{RIOP_ENONFINITE, "non-finite value reached a norm in SDMM"};
+}
+
+template <typename R> static void apply_q_run(riop_plan *p, const void *x, void *out, hipStream_t s) {
+    const long N = (long)p->n * p->n;
+    ensure_work(p);
+    gram_sorted<R>(p, x, p->sd.tmpN.ptr, s);
+    hipLaunchKernelGGL(add_2x<R>, RB(), RT(), 0, s, p->sd.tmpN.as<C<R>>(), static_cast<const C<R> *>(x),
+                       static_cast<C<R> *>(out), N);
+    RIOP_HIP(hipGetLastError());
+}
+
+template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x, int n_iter, double *rr_out,
+                                           hipStream_t s) {
+    int slot = SLOT_RR0;
+    cg_run<R>(p, b, x, n_iter, &slot, s);
+    if (rr_out) {
+        hipLaunchKernelGGL(slot_to_scalar, dim3(1), RT(), 0, s, (const double *)p->sd.partials.as<double>(), slot,
+                           p->sd.scalars.as<double>(), (int)SC_RRFINAL);
+        RIOP_HIP(hipGetLastError());
+        RIOP_HIP(hipMemcpyAsync(rr_out, p->sd.scalars.as<double>() + SC_RRFINAL, sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        RIOP_HIP(hipStreamSynchronize(s));
+    }
+}
+
+template <typename R> static void gamma_entry(riop_plan *p, const void *y, double beta, double *g, hipStream_t s) {
+    gamma_run<R>(p, y, 1, beta, s);
+    RIOP_HIP(hipMemcpyAsync(g, p->sd.scalars.as<double>() + SC_GAMMA, sizeof(double), hipMemcpyDeviceToHost, s));
+    RIOP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace riop
+
+using namespace riop;
+
+template <typename F> static riop_status guarded2(F &&f) {
+    try {
+        clear_error();
+        f();
+        return RIOP_OK;
+    } catch (const Error &e) {
+        set_error("%s", e.msg.c_str());
+        return e.status;
+    } catch (...) {
+        set_error("unexpected failure");
+        return RIOP_EDEVICE;
+    }
+}
+
+static void check_plan2(const riop_plan *p) {
+    RIOP_REQUIRE(p, RIOP_EINVAL, "plan is NULL");
+    int dev = -1;
+    RIOP_HIP(hipGetDevice(&dev));
+    RIOP_REQUIRE(dev == p->device, RIOP_EINVAL, "plan belongs to another device than the current one");
+}
+
+extern "C" {
+
+riop_status riop_apply_q(riop_plan *p, const void *x, void *out, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(x && out && x != out, RIOP_EINVAL, "x and out must be distinct non-NULL pointers");
+        if (p->prec == RIOP_F64)
+            apply_q_run<double>(p, x, out, static_cast<hipStream_t>(stream));
+        else
+            apply_q_run<float>(p, x, out, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_cg(riop_plan *p, const void *b, void *x, int32_t n_iter, double *rr_out, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(b && x && b != x, RIOP_EINVAL, "b and x must be distinct non-NULL pointers");
+        RIOP_REQUIRE(n_iter >= 0, RIOP_EINVAL, "n_iter must be >= 0");
+        if (p->prec == RIOP_F64)
+            cg_entry<double>(p, b, x, n_iter, rr_out, static_cast<hipStream_t>(stream));
+        else
+            cg_entry<float>(p, b, x, n_iter, rr_out, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_gamma(riop_plan *p, const void *y, double beta, double *gamma, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(gamma && (y || p->M == 0), RIOP_EINVAL, "NULL argument");
+        if (p->prec == RIOP_F64)
+            gamma_entry<double>(p, y, beta, gamma, static_cast<hipStream_t>(stream));
+        else
+            gamma_entry<float>(p, y, beta, gamma, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, void *x_inout,
+                      riop_sdmm_stats *stats, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(prm, RIOP_EINVAL, "params is NULL");
+        RIOP_REQUIRE(y || p->M == 0, RIOP_EINVAL, "y is NULL");
+        RIOP_REQUIRE(eps > 0 && std::isfinite(eps), RIOP_EINVAL, "eps must be positive and finite");
+        RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0, RIOP_EINVAL, "T and n_cg must be >= 0");
+        RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        if (p->prec == RIOP_F64)
+            sdmm_run<double>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
+        else
+            sdmm_run<float>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+"""GPU SDMM (Algorithm 1) against the FP64 oracle, called through the C ABI.
+
+After a fixed number of iterations the GPU iterate must match the oracle's
+iterate with the same parameters: relative L2 <= 1e-10 (FP64), <= 1e-4 (FP32
+bulk with FP64 norms and CG scalars).  The per-iteration halting quantities and
+the dual variables are compared too.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nufft, sdmm as osdmm, wavelets
+from tests.gpu_helpers import announce, device, host, rel, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _problem(c: W.Config, prec: str):
+    x_true, uv = W.config_inputs(c)
+    if prec == "f32":
+        uv = uv.astype(np.float32).astype(np.float64)
+    op = nufft.Operator(c.n, uv, c.J)
+    y0 = op.phi(x_true)
+    sig = osdmm.noise_sigma(y0, c.isnr_db)
+    y = y0 + sig * W.unit_complex_noise(c.M, W.rng(c.cfg, W.STREAM_NOISE))
+    if prec == "f32":
+        y = y.astype(np.complex64).astype(np.complex128)
+    eps = osdmm.noise_bound(c.M, sig)
+    return x_true, uv, op, y, eps
+
+
+def _plan(c, uv, prec, mask=wavelets.FULL_MASK):
+    from paper_1307_4370_amd import Plan
+    return Plan(c.n, to_dev(uv, prec), J=c.J, levels=c.levels, dict_mask=mask, prec=prec)
+
+
+SMALL = W.Config(50, "sdmm-small", n=32, M=700, J=6, levels=2, T=6, n_gauss=4, n_points=10)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_sdmm_small_matches_oracle(prec, tol):
+    device()
+    announce(f"sdmm small {prec}")
+    c = SMALL
+    x_true, uv, op, y, eps = _problem(c, prec)
+    sara = wavelets.Sara(c.n, c.levels)
+    xo, st, hist, gam = osdmm.sdmm(y, eps, op, sara, T=c.T, n_cg=8)
+    plan = _plan(c, uv, prec)
+    xg, stats, ghist, gstate = plan.sdmm(to_dev(y, prec), eps, T=c.T, n_cg=8)
+    assert stats["iters"] == c.T
+    assert stats["gamma"] == pytest.approx(gam, rel=1e-12 if prec == "f64" else 1e-5)
+    assert rel(host(xg), xo) <= tol
+    assert rel(host(gstate["z1"]), st.z1) <= tol * 10
+    assert rel(host(gstate["z2"]), st.z2) <= tol * 10
+    assert rel(host(gstate["z3"]), st.z3) <= tol * 10
+    for t in range(1, c.T):
+        f1, zeta, nu, _ = ghist[t]
+        assert f1 == pytest.approx(hist[t]["f1"], rel=tol)
+        assert nu == pytest.approx(hist[t]["nu"], rel=tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_sdmm_config1_fixed_iterations(prec, tol):
+    """64 x 64 sky, M = 2048, J = 6, SARA at 3 levels: 100 iterations."""
+    device()
+    c = W.C1
+    announce(f"sdmm C1 {prec} T={c.T}")
+    x_true, uv, op, y, eps = _problem(c, prec)
+    sara = wavelets.Sara(c.n, c.levels)
+    xo, _, hist, gam = osdmm.sdmm(y, eps, op, sara, T=c.T, n_cg=c.n_cg)
+    plan = _plan(c, uv, prec)
+    xg, stats, ghist, _ = plan.sdmm(to_dev(y, prec), eps, T=c.T, n_cg=c.n_cg)
+    assert rel(host(xg), xo) <= tol
+    snr_o = osdmm.snr_db(x_true, np.real(xo))
+    snr_g = osdmm.snr_db(x_true, np.real(host(xg)))
+    assert snr_g == pytest.approx(snr_o, abs=0.01)
+    assert ghist[-1][2] == pytest.approx(hist[-1]["nu"], rel=tol)
+
+
+def test_sdmm_resume_equals_single_run():
+    device()
+    announce("sdmm resume")
+    c = SMALL
+    _, uv, op, y, eps = _problem(c, "f64")
+    plan = _plan(c, uv, "f64")
+    yd = to_dev(y, "f64")
+    xa, sa, _, _ = plan.sdmm(yd, eps, T=6, n_cg=8, gamma=0.01)
+    x1, s1, _, st = plan.sdmm(yd, eps, T=2, n_cg=8, gamma=0.01)
+    xb, sb, _, _ = plan.sdmm(yd, eps, T=4, n_cg=8, gamma=0.01, x0=x1, state=st)
+    assert rel(host(xb), host(xa)) <= 1e-14
+    assert sb["f1"] == pytest.approx(sa["f1"], rel=1e-14)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_sdmm_weighted_and_subdictionary(prec, tol):
+    device()
+    announce(f"sdmm weighted {prec}")
+    c = SMALL
+    _, uv, op, y, eps = _problem(c, prec)
+    mask = 0b100000011
+    sara = wavelets.Sara(c.n, c.levels, mask)
+    wts = W.rng(51, 0).uniform(0.5, 2.0, size=(sara.q, c.n, c.n))
+    if prec == "f32":
+        wts = wts.astype(np.float32).astype(np.float64)
+    xo, _, _, gam = osdmm.sdmm(y, eps, op, sara, T=5, n_cg=6, weights=wts)
+    plan = _plan(c, uv, prec, mask=mask)
+    xg, _, _, _ = plan.sdmm(to_dev(y, prec), eps, T=5, n_cg=6, weights=to_dev(wts, prec))
+    assert rel(host(xg), xo) <= tol
+
+
+def test_sdmm_large_eps_gives_zero():
+    device()
+    announce("sdmm eps >= ||y||")
+    c = SMALL
+    _, uv, op, y, eps = _problem(c, "f64")
+    plan = _plan(c, uv, "f64")
+    xg, stats, _, _ = plan.sdmm(to_dev(y, "f64"), 1.01 * np.linalg.norm(y), T=4, n_cg=6)
+    assert np.all(host(xg) == 0)
+
+
+def test_sdmm_rejects_bad_arguments():
+    device()
+    announce("sdmm bad args")
+    from paper_1307_4370_amd import RiopError
+    c = SMALL
+    _, uv, op, y, eps = _problem(c, "f64")
+    plan = _plan(c, uv, "f64")
+    for bad_eps in (0.0, -1.0, float("inf")):
+        with pytest.raises(RiopError):
+            plan.sdmm(to_dev(y, "f64"), bad_eps, T=1)

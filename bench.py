@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the SDMM imaging hot path on one MI355X.
+
+Workload: 1024 x 1024 sky (200 elliptical Gaussians + 2000 point sources),
+M = 4194304 continuous visibilities (2-D Gaussian variable-density coverage,
+sigma = pi/4), oversampling 2 (2048 x 2048 grid), 8 x 8 Kaiser-Bessel kernel,
+SARA (Dirac + Db1..Db8) at 4 levels, input SNR 30 dB.
+
+A step is one SDMM iteration (Algorithm 1): CG x-update with n_cg = 16 on
+Q = Phi^dagger Phi + 2I (17 Phi/Phi^dagger pairs with the initial residual),
+the l1 prox fused into Psi^dagger, the l2-ball prox around Phi x, the
+positivity prox and the next right-hand side (one more pair and one
+Psi^dagger / Psi pair).  value = visibilities through Phi + Phi^dagger per
+second = M x 18 pairs x steps / time.  Inputs are resident in HBM before the
+timed region.  FP32 storage and arithmetic with FP64 norms and CG scalars.
+
+Also reported: SDMM iterations/s, the same in plain FP64, stand-alone
+Phi + Phi^dagger pair throughput, per-kernel times and the roofline of the
+dominant kernel (HIP events on the library's stream), and the CPU oracle on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "visibilities/s through Phi+Phi^dagger and SDMM iters/s at 1024^2, FP32 vs FP64 plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind: str, n: int, M: int, cbytes: int):
+    """Bytes the method must move per launch of one kernel kind.
+
+    N = n^2 pixels, grid K^2 = 4N cells; complex = cbytes, (u, v) = cbytes.
+      fft_fwd_col: read x (N), write the K x n intermediate (2N)      -> 3N complex
+      fft_fwd_row: read 2N, write the grid 4N                         -> 6N
+      fft_adj_row: read the grid 4N, write 2N                         -> 6N
+      fft_adj_col: read 2N, write x N                                 -> 3N
+      degrid:      read the grid 4N + (u, v) M, write y M            -> 4N + 2M
+      grid:        read (u, v) M + values M, write the grid 4N       -> 4N + 2M
+      grid_zero:   write the grid 4N
+    """
+    N = n * n
+    table = {"fft_fwd_col": 3 * N, "fft_fwd_row": 6 * N, "fft_adj_row": 6 * N, "fft_adj_col": 3 * N,
+             "degrid": 4 * N + 2 * M, "grid": 4 * N + 2 * M, "grid_zero": 4 * N}
+    return table[kind] * cbytes if kind in table else None
+
+
+def cpu_baseline(n, J, uv, x_true, sample_m=262144, pairs=2):
+    """FP64 oracle Phi + Phi^dagger on the host, bounded sample.
+
+    The grid FFTs run at full size; the interpolation (G, G^T) runs on the first
+    ``sample_m`` visibilities and its time is scaled by M / sample_m, since its
+    cost is linear in M.  Building G (once per coverage) is not timed.
+    """
+    import numpy as np
+    from oracle import nufft
+    M = len(uv)
+    t0 = time.perf_counter()
+    op = nufft.Operator(n, uv[:sample_m], J)
+    t_build = time.perf_counter() - t0
+    x = x_true.astype(np.complex128)
+    t_fft = t_g = 0.0
+    for _ in range(pairs):
+        t0 = time.perf_counter()
+        X = op.forward_grid(x)
+        t1 = time.perf_counter()
+        y = op.degrid(X)
+        t2 = time.perf_counter()
+        grid = op.grid_adj(y)
+        t3 = time.perf_counter()
+        xa = np.fft.ifft2(grid)[: n, : n]
+        t4 = time.perf_counter()
+        t_fft += (t1 - t0) + (t4 - t3)
+        t_g += (t2 - t1) + (t3 - t2)
+    per_pair = (t_fft + t_g * (M / sample_m)) / pairs
+    return {
+        "value": M / per_pair, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{pairs} Phi+Phi^dagger pairs of the FP64 oracle on the 1024^2 workload: full-size "
+                   f"2048^2 FFTs, interpolation on {sample_m} of {M} visibilities scaled by M/{sample_m}; "
+                   f"G build ({t_build:.1f} s) not timed; numpy/scipy single-threaded"),
+        "seconds_per_pair": per_pair,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-cg", type=int, default=16)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--pairs", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the visibilities would be sharded); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1307_4370_amd import Plan, noise_bound
+
+    c = W.C3
+    n, M, J, L, ncg = c.n, c.M, c.J, c.levels, args.n_cg
+    dev = torch.device("cuda:0")
+    log(f"workload n={n} M={M} J={J} levels={L} n_cg={ncg}")
+    x_true, uv = W.config_inputs(c)
+    noise = W.unit_complex_noise(M, W.rng(c.cfg, W.STREAM_NOISE))
+
+    def setup(prec):
+        rd = np.float32 if prec == "f32" else np.float64
+        cd = torch.complex64 if prec == "f32" else torch.complex128
+        uvd = torch.tensor(uv.astype(rd), device=dev)
+        plan = Plan(n, uvd, J=J, levels=L, prec=prec)
+        xd = torch.tensor(x_true, device=dev).to(cd)
+        y0 = plan.phi(xd)
+        torch.cuda.synchronize()
+        y0h = y0.cpu().numpy().astype(np.complex128)
+        sigma = float(np.linalg.norm(y0h)) * 10 ** (-c.isnr_db / 20) / math.sqrt(M)
+        y = torch.tensor(y0h + sigma * noise, device=dev).to(cd)
+        eps = noise_bound(M, sigma)
+        return plan, xd, y, eps
+
+    # ---- FP32 SDMM (the timed steps) -----------------------------------------
+    plan, xd, y, eps = setup("f32")
+    log(f"plan: {plan.info()}")
+    x, st, _, state = plan.sdmm(y, eps, T=args.warmup, n_cg=ncg)
+    gamma = st["gamma"]
+    torch.cuda.synchronize()
+    plan.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st, hist, state = plan.sdmm(y, eps, T=args.steps, n_cg=ncg, gamma=gamma, x0=x, state=state)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernels = plan.timing_read()
+    plan.timing(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    pairs_per_step = ncg + 2
+    value = M * pairs_per_step / (ms_step * 1e-3)
+    iters_s = 1e3 / ms_step
+    log(f"fp32: {ms_step:.3f} ms/iteration, {value:.4g} vis/s, nu={st['nu']:.4f}")
+
+    # Roofline of the dominant kernel (largest total time in the timed region).
+    cb = 8
+    dom = max((k for k in kernels if algorithmic_bytes(k, n, M, cb) is not None), key=lambda k: kernels[k][0])
+    tot_ms, launches = kernels[dom]
+    avg_s = tot_ms * 1e-3 / max(1, launches)
+    ach = algorithmic_bytes(dom, n, M, cb) / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(avg_s * 1e6, 2)}
+    kern = {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                "avg_us": round(v[0] * 1e3 / v[1], 2) if v[1] else None,
+                "algorithmic_GBs": (round(algorithmic_bytes(k, n, M, cb) / (v[0] * 1e-3 / v[1]) / 1e9, 1)
+                                    if v[1] and algorithmic_bytes(k, n, M, cb) else None)}
+            for k, v in kernels.items() if v[1]}
+
+    # Stand-alone Phi + Phi^dagger pairs (caller order and plan order).
+    def pair_rate(p, xin, yin, sorted_, reps):
+        for _ in range(2):
+            p.phi_adj(p.phi(xin, yin, sorted=sorted_), sorted=sorted_)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            p.phi_adj(p.phi(xin, yin, sorted=sorted_), sorted=sorted_)
+        torch.cuda.synchronize()
+        return M * reps / (time.perf_counter() - a)
+
+    ybuf = torch.empty(M, dtype=torch.complex64, device=dev)
+    pairs32 = {"caller_order": pair_rate(plan, xd, ybuf, False, args.pairs),
+               "plan_order": pair_rate(plan, xd, ybuf, True, args.pairs)}
+    log(f"fp32 pairs: {pairs32}")
+    del ybuf
+
+    fp64 = None
+    if not args.no_fp64:
+        plan64, xd64, y64, eps64 = setup("f64")
+        x64, st64, _, state64 = plan64.sdmm(y64, eps64, T=1, n_cg=ncg)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plan64.sdmm(y64, eps64, T=args.fp64_steps, n_cg=ncg, gamma=st64["gamma"], x0=x64, state=state64)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - a) * 1e3 / args.fp64_steps
+        yb64 = torch.empty(M, dtype=torch.complex128, device=dev)
+        fp64 = {"ms_per_step": round(ms64, 3), "sdmm_iters_per_s": round(1e3 / ms64, 3),
+                "visibilities_per_s": M * pairs_per_step / (ms64 * 1e-3),
+                "pair_visibilities_per_s": pair_rate(plan64, xd64, yb64, False, max(2, args.pairs // 4))}
+        log(f"fp64: {fp64}")
+        del plan64, yb64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(n, J, uv, x_true)
+        log(f"cpu: {cpu['value']:.4g} vis/s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "visibilities/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"{c.name}: {n}x{n} sky, M={M} Gaussian-density (u,v), oversampling 2, "
+                                f"KB J={J}, SARA Dirac+Db1-8 at {L} levels, one SDMM iteration per step "
+                                f"with n_cg={ncg}"),
+                   "n": n, "M": M, "J": J, "levels": L, "n_cg": ncg, "pairs_per_step": pairs_per_step},
+        "sdmm_iters_per_s": round(iters_s, 3),
+        "pair_visibilities_per_s": pairs32,
+        "fp64": fp64,
+        "roofline": roofline,
+        "kernels": kern,
+        "cpu_baseline": cpu,
+        "final_nu": st["nu"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -215,6 +215,40 @@ riop_status riop_sdmm(riop_plan *plan, const void *y, double eps,
                       const riop_sdmm_params *params, void *x_inout,
                       riop_sdmm_stats *stats, void *stream);
 
+/* The same run in three phases, for callers that capture the iterations in a
+ * HIP graph or interleave several plans.
+ *   riop_sdmm_init    Algorithm 1 steps 1-3 (or a resumed state), the penalty
+ *                     gamma and y in plan order; allocates the plan's SDMM
+ *                     workspace on first use.  params->T sets how many
+ *                     iterations the per-iteration history keeps.  Asynchronous.
+ *   riop_sdmm_step    enqueue `iterations` iterations (steps 5-9 and the halting
+ *                     quantities).  No allocation, no host synchronisation:
+ *                     may be captured in a HIP graph and the graph replayed; the
+ *                     iteration counter lives on the device.
+ *   riop_sdmm_finish  copy x (x_out, nullable) and, if params is non-NULL, the
+ *                     state (params->z1, z2, z3, rhs) and history out; fills
+ *                     stats.  Synchronises `stream`.
+ * No early stopping in this form. */
+riop_status riop_sdmm_init(riop_plan *plan, const void *y, double eps,
+                           const riop_sdmm_params *params, const void *x0, void *stream);
+riop_status riop_sdmm_step(riop_plan *plan, int32_t iterations, void *stream);
+riop_status riop_sdmm_finish(riop_plan *plan, const riop_sdmm_params *params, void *x_out,
+                             riop_sdmm_stats *stats, void *stream);
+
+/* Kernel timing with HIP events (for benchmarks).  When enabled, every kernel
+ * launch of the plan is bracketed by a pair of events recorded on the launch
+ * stream and attributed to a kernel kind (see riop_timing_name).  Enabling
+ * resets the accumulators; disabling stops recording.  No effect on results. */
+riop_status riop_timing_enable(riop_plan *plan, int32_t on);
+
+/* Total time (ms) and number of launches of one kernel kind since the last
+ * enable.  Synchronises with the recorded events.  kind in [0, riop_timing_kinds()). */
+riop_status riop_timing_read(riop_plan *plan, int32_t kind, double *total_ms, int64_t *launches);
+
+/* Number of kernel kinds and the name of one ("degrid", "grid", ...). */
+int32_t riop_timing_kinds(void);
+const char *riop_timing_name(int32_t kind);
+
 /* Message for the last failure on the calling thread ("" if none). */
 const char *riop_last_error(void);
 

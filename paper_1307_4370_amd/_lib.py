@@ -26,7 +26,8 @@ STATUS = {0: "RIOP_OK", -1: "RIOP_EINVAL", -2: "RIOP_ESHAPE", -3: "RIOP_ENOMEM",
 EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan_layout",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_gamma",
-           "riop_sdmm", "riop_last_error", "riop_version")
+           "riop_sdmm", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
+           "riop_timing_name", "riop_last_error", "riop_version")
 
 
 class RiopError(RuntimeError):
@@ -86,9 +87,17 @@ def lib() -> ctypes.CDLL:
         L.riop_gamma.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), vp]
         L.riop_sdmm.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp,
                                 ctypes.POINTER(SdmmStats), vp]
+        L.riop_sdmm_init.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp, vp]
+        L.riop_sdmm_step.argtypes = [vp, i32, vp]
+        L.riop_sdmm_finish.argtypes = [vp, ctypes.POINTER(SdmmParams), vp, ctypes.POINTER(SdmmStats), vp]
+        L.riop_timing_enable.argtypes = [vp, i32]
+        L.riop_timing_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+        L.riop_timing_kinds.argtypes = []
+        L.riop_timing_name.argtypes = [i32]
         for name in EXPORTS:
-            if name not in ("riop_last_error", "riop_version"):
+            if name not in ("riop_last_error", "riop_version", "riop_timing_name"):
                 getattr(L, name).restype = ctypes.c_int
+        L.riop_timing_name.restype = ctypes.c_char_p
         L.riop_last_error.restype = ctypes.c_char_p
         L.riop_version.restype = ctypes.c_char_p
         _lib = L
@@ -160,6 +169,19 @@ class Plan:
         inf = Info()
         _check(lib().riop_plan_info(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def timing(self, on: bool = True):
+        """Enable (and reset) or disable per-kernel event timing."""
+        _check(lib().riop_timing_enable(self._h, int(on)))
+
+    def timing_read(self) -> dict:
+        """{kernel kind: (total ms, launches)} since timing was enabled."""
+        out = {}
+        for k in range(lib().riop_timing_kinds()):
+            ms, cnt = ctypes.c_double(), ctypes.c_int64()
+            _check(lib().riop_timing_read(self._h, k, ctypes.byref(ms), ctypes.byref(cnt)))
+            out[lib().riop_timing_name(k).decode()] = (ms.value, cnt.value)
+        return out
 
     def layout(self, stream=None):
         inf = self.info()

@@ -28,6 +28,63 @@ void set_error(const char *fmt, ...) {
 void clear_error() { g_err.clear(); }
 
 // ---------------------------------------------------------------------------
+// Event timing.
+
+Timing::~Timing() {
+    for (auto &e : pending) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+hipEvent_t Timing::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    RIOP_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Timing::flush() {
+    for (auto &e : pending) {
+        RIOP_HIP(hipEventSynchronize(e.second.second));
+        float ms = 0;
+        RIOP_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+        total_ms[e.first] += ms;
+        launches[e.first] += 1;
+        pool.push_back(e.second.first);
+        pool.push_back(e.second.second);
+    }
+    pending.clear();
+}
+
+TimedScope::TimedScope(riop_plan *p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
+    if (!p->timing.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    a = p->timing.get();
+    RIOP_HIP(hipEventRecord(a, s));
+}
+
+TimedScope::~TimedScope() {
+    if (!a) return;
+    try {
+        hipEvent_t b = p->timing.get();
+        (void)hipEventRecord(b, s);
+        p->timing.pending.push_back({kind, {a, b}});
+    } catch (...) {
+    }
+}
+
+static const char *kKindNames[KK_COUNT] = {"fft_fwd_col", "fft_fwd_row", "fft_adj_row", "fft_adj_col",
+                                           "degrid",      "grid",        "grid_zero",   "psi_adj",
+                                           "psi",         "vector"};
+
+// ---------------------------------------------------------------------------
 // Kaiser-Bessel kernel on the host.
 
 static double bessel_i0(double z) {
@@ -406,6 +463,32 @@ riop_status riop_plan_info(const riop_plan *p, riop_info *info) {
         info->device_bytes = p->device_bytes + extra;
     });
 }
+
+riop_status riop_timing_enable(riop_plan *p, int32_t on) {
+    return guarded([&] {
+        check_plan(p);
+        p->timing.flush();
+        p->timing.on = on != 0;
+        for (int k = 0; k < KK_COUNT; ++k) {
+            p->timing.total_ms[k] = 0;
+            p->timing.launches[k] = 0;
+        }
+    });
+}
+
+riop_status riop_timing_read(riop_plan *p, int32_t kind, double *total_ms, int64_t *launches) {
+    return guarded([&] {
+        check_plan(p);
+        RIOP_REQUIRE(kind >= 0 && kind < KK_COUNT, RIOP_EINVAL, "kernel kind out of range");
+        p->timing.flush();
+        if (total_ms) *total_ms = p->timing.total_ms[kind];
+        if (launches) *launches = p->timing.launches[kind];
+    });
+}
+
+int32_t riop_timing_kinds(void) { return KK_COUNT; }
+
+const char *riop_timing_name(int32_t kind) { return kind >= 0 && kind < KK_COUNT ? kKindNames[kind] : ""; }
 
 riop_status riop_plan_layout(const riop_plan *p, int32_t *perm, uint32_t *cell, int32_t *tile_start,
                              void *stream) {

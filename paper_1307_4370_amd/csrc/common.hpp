@@ -99,6 +99,23 @@ struct FftPlan {
     DevBuf twiddle;         // N complex: exp(-2 pi i m / N)
 };
 
+// Kernel kinds for event timing.
+enum KernelKind {
+    KK_FFT_FWD_COL = 0, KK_FFT_FWD_ROW, KK_FFT_ADJ_ROW, KK_FFT_ADJ_COL,
+    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_COUNT
+};
+
+struct Timing {
+    bool on = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[KK_COUNT] = {};
+    int64_t launches[KK_COUNT] = {};
+    ~Timing();
+    hipEvent_t get();
+    void flush();
+};
+
 // Device-side SDMM workspace (allocated on first use).
 struct SdmmWork {
     bool ready = false;
@@ -108,6 +125,10 @@ struct SdmmWork {
     DevBuf partials;        // doubles for block reductions
     DevBuf scalars;         // doubles: scalar slots
     DevBuf history;         // doubles, 4 per iteration
+    int hist_cap = 0;       // iterations the history buffer holds
+    int n_cg = 0;
+    const void *weights = nullptr;
+    bool initialised = false;
 };
 
 }  // namespace riop
@@ -156,6 +177,7 @@ struct riop_plan {
     size_t ll_stride = 0;   // complex entries per basis in `ll`
 
     riop::SdmmWork sd;
+    riop::Timing timing;
     int64_t device_bytes = 0;
 };
 
@@ -186,6 +208,17 @@ template <typename R> struct Prox1 {
 };
 template <typename R>
 void launch_psi_adj_prox(riop_plan *p, const void *x, const Prox1<R> &px, hipStream_t st);
+
+// Brackets the kernel launches of its lifetime with timing events when the
+// plan's timing is enabled.
+struct TimedScope {
+    riop_plan *p;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    TimedScope(riop_plan *p_, int kind_, hipStream_t s_);
+    ~TimedScope();
+};
 
 void build_fft_plan(riop_plan *p, hipStream_t st);
 void build_layout(riop_plan *p, const void *uv, hipStream_t st);

@@ -276,7 +276,7 @@ void build_fft_plan(riop_plan *p, hipStream_t st) {
 }
 
 template <typename R, int SGN, bool COLS>
-static void launch_pass(riop_plan *p, FftArgs<R> a, hipStream_t st) {
+static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
     const FftPlan &f = p->fft;
     a.N = f.N;
     a.nstages = f.nstages;
@@ -299,6 +299,7 @@ static void launch_pass(riop_plan *p, FftArgs<R> a, hipStream_t st) {
     RIOP_REQUIRE(threads <= 1024, RIOP_ENOTSUP, "FFT block too large");
     const int blocks = (a.nbatch + Cb - 1) / Cb;
     const size_t lds = line * Cb;
+    TimedScope ts(p, kind, st);
     if (E == 8)
         hipLaunchKernelGGL((fft_pass<R, 8, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a);
     else
@@ -325,7 +326,7 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
     a.dbt = d;
     a.factors_at_input = 1;
     a.scale = R(1) / R(K);
-    launch_pass<R, -1, true>(p, a, st);
+    launch_pass<R, -1, true>(p, a, KK_FFT_FWD_COL, st);
     // Pass 2: rows k1 of tmp, transform over q (padded) -> grid row k1.
     FftArgs<R> b{};
     b.in = p->tmp.as<C<R>>();
@@ -340,7 +341,7 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
     b.crop_out = 0;
     b.factors_at_input = 1;
     b.scale = R(1);
-    launch_pass<R, -1, false>(p, b, st);
+    launch_pass<R, -1, false>(p, b, KK_FFT_FWD_ROW, st);
 }
 
 template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st) {
@@ -360,7 +361,7 @@ template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStre
     a.crop_out = 1;
     a.factors_at_input = 0;
     a.scale = R(1);
-    launch_pass<R, +1, false>(p, a, st);
+    launch_pass<R, +1, false>(p, a, KK_FFT_ADJ_ROW, st);
     // Pass 2: columns q of tmp, inverse over k1, crop to p, correct by d(p) d(q), 1/K.
     FftArgs<R> b{};
     b.in = p->tmp.as<C<R>>();
@@ -377,7 +378,7 @@ template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStre
     b.dbt = d;
     b.factors_at_input = 0;
     b.scale = R(1) / R(K);
-    launch_pass<R, +1, true>(p, b, st);
+    launch_pass<R, +1, true>(p, b, KK_FFT_ADJ_COL, st);
 }
 
 template void launch_phi_fft_forward<float>(riop_plan *, const void *, hipStream_t);

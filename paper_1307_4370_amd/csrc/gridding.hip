@@ -461,6 +461,7 @@ template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, 
     a.order_user = order_user;
     const int W = p->tile + p->J - 1;
     const size_t lds = sizeof(C<R>) * W * W;
+    TimedScope ts(p, KK_DEGRID, st);
     switch (p->J) {
 #define DG(JJ) \
     case JJ:                                                                                          \
@@ -477,13 +478,17 @@ template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, 
 }
 
 template <typename R> void launch_grid(riop_plan *p, const void *y, int order_user, hipStream_t st) {
-    launch_fill_zero<R>(p->grid.ptr, (size_t)p->K * p->K, st);
+    {
+        TimedScope tz(p, KK_GRID_ZERO, st);
+        launch_fill_zero<R>(p->grid.ptr, (size_t)p->K * p->K, st);
+    }
     if (p->nunits == 0) return;
     GridArgs<R> a = grid_args<R>(p);
     a.vin = static_cast<const C<R> *>(y);
     a.order_user = order_user;
     const int W = p->tile + p->J - 1;
     const size_t lds = sizeof(R) * 2 * W * W;
+    TimedScope ts(p, KK_GRID, st);
     switch (p->J) {
 #define GK(JJ) \
     case JJ:                                                                                          \

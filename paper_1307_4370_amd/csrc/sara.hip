@@ -332,6 +332,7 @@ static void psi_adj_impl(riop_plan *p, const void *x, void *alpha, const Prox1<R
         d.plane[0] = dirac_plane;
         const long N = (long)n * n;
         const int blocks = (int)std::min<long>((N + 255) / 256, 4096);
+        TimedScope ts(p, KK_PSI_ADJ, st);
         hipLaunchKernelGGL(dirac_analysis<R>, dim3(blocks), dim3(256), 0, st, d, static_cast<const C<R> *>(x));
         RIOP_HIP(hipGetLastError());
     }
@@ -352,6 +353,7 @@ static void psi_adj_impl(riop_plan *p, const void *x, void *alpha, const Prox1<R
         a.ll_out = a.last ? nullptr : ll + ll_offset(n, lev);
         a.ll_bstride = (long)p->ll_stride;
         const int tiles = half / a.TO;
+        TimedScope ts(p, KK_PSI_ADJ, st);
         hipLaunchKernelGGL(dwt_analysis<R>, dim3(tiles * tiles, nb), dim3(256), ana_lds<R>(a.TO), st, a);
         RIOP_HIP(hipGetLastError());
     }
@@ -389,6 +391,7 @@ template <typename R> void launch_psi(riop_plan *p, const void *alpha, void *x, 
     if (nb == 0) {
         const long N = (long)n * n;
         const int blocks = (int)std::min<long>((N + 255) / 256, 4096);
+        TimedScope ts(p, KK_PSI, st);
         hipLaunchKernelGGL(dirac_only_synthesis<R>, dim3(blocks), dim3(256), 0, st, a.alpha, a.dirac_plane,
                            a.x, N, a.scale);
         RIOP_HIP(hipGetLastError());
@@ -403,6 +406,7 @@ template <typename R> void launch_psi(riop_plan *p, const void *alpha, void *x, 
         a.ll_in = a.coarsest ? nullptr : ll + ll_offset(n, lev);
         a.ll_in_bstride = (long)p->ll_stride;
         const int TS = 2 * a.TO, tiles = s / TS;
+        TimedScope ts(p, KK_PSI, st);
         if (lev > 1) {
             a.ll_out = ll + ll_offset(n, lev - 1);
             a.ll_out_bstride = (long)p->ll_stride;

@@ -24,7 +24,7 @@ constexpr int kRedThreads = 256;
 // Partial-sum slots (each kRedBlocks doubles).
 enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, kSlots };
 // Scalar slots.
-enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, kScalars };
+enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, kScalars };
 
 __device__ inline double block_sum(double v) {
     __shared__ double red[kRedThreads];
@@ -237,25 +237,37 @@ template <typename R> __global__ void add3(const C<R> *a, const C<R> *b, const C
     }
 }
 
-// history[t] = {f1, zeta, nu, final CG rr}; f1_prev <- f1
-__global__ void record_stats(const double *partials, double *scalars, double *hist, int t, int rr_slot) {
+// history[t] = {f1, zeta, nu, final CG rr} with t the device iteration
+// counter (so a captured graph can be replayed); f1_prev <- f1; t <- t + 1.
+__global__ void record_stats(const double *partials, double *scalars, double *hist, int cap, int rr_slot) {
     const double nu2 = slot_sum(partials, SLOT_NU);
     const double rr = slot_sum(partials, rr_slot);
     if (threadIdx.x == 0) {
+        const int t = (int)scalars[SC_ITER];
         const double f1 = scalars[SC_F1ACC];
         const double prev = scalars[SC_F1PREV];
         const double zeta = prev == 0.0 ? INFINITY : fabs(f1 - prev) / fabs(prev);
-        hist[4 * t + 0] = f1;
-        hist[4 * t + 1] = zeta;
-        hist[4 * t + 2] = sqrt(nu2) / scalars[SC_EPS];
-        hist[4 * t + 3] = rr;
+        if (t < cap) {
+            hist[4 * t + 0] = f1;
+            hist[4 * t + 1] = zeta;
+            hist[4 * t + 2] = sqrt(nu2) / scalars[SC_EPS];
+            hist[4 * t + 3] = rr;
+        }
         scalars[SC_F1PREV] = f1;
         scalars[SC_RRFINAL] = rr;
+        scalars[SC_ITER] = (double)(t + 1);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host side.
+
+// Launch of a vector / reduction kernel, timed as the "vector" kind.
+#define VEC_LAUNCH(p, ...)                          \
+    do {                                            \
+        TimedScope ts_((p), KK_VECTOR, s);          \
+        hipLaunchKernelGGL(__VA_ARGS__);            \
+    } while (0)
 
 static dim3 RB() { return dim3(kRedBlocks); }
 static dim3 RT() { return dim3(kRedThreads); }
@@ -298,17 +310,17 @@ static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_
     const long N = (long)p->n * p->n;
     double *part = w.partials.as<double>();
     gram_sorted<R>(p, x, w.qp.ptr, s);
-    hipLaunchKernelGGL(cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
+    VEC_LAUNCH(p, cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
                        w.qp.as<C<R>>(), w.r.as<C<R>>(), w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
     RIOP_HIP(hipGetLastError());
     int cur = SLOT_RR0;
     for (int k = 0; k < n_iter; ++k) {
         const int nxt = cur == SLOT_RR0 ? SLOT_RR1 : SLOT_RR0;
         gram_sorted<R>(p, w.p.ptr, w.qp.ptr, s);
-        hipLaunchKernelGGL(cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
-        hipLaunchKernelGGL(cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r.as<C<R>>(), w.p.as<C<R>>(),
+        VEC_LAUNCH(p, cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
+        VEC_LAUNCH(p, cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r.as<C<R>>(), w.p.as<C<R>>(),
                            w.qp.as<C<R>>(), N, part, cur, (int)SLOT_PQ, nxt);
-        hipLaunchKernelGGL(cg_direction<R>, RB(), RT(), 0, s, w.r.as<C<R>>(), w.p.as<C<R>>(), N,
+        VEC_LAUNCH(p, cg_direction<R>, RB(), RT(), 0, s, w.r.as<C<R>>(), w.p.as<C<R>>(), N,
                            (const double *)part, cur, nxt);
         RIOP_HIP(hipGetLastError());
         cur = nxt;
@@ -324,144 +336,173 @@ template <typename R> static void gamma_run(riop_plan *p, const void *y_sorted_o
     launch_grid<R>(p, y_sorted_or_user, user, s);
     launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
     launch_psi_adj<R>(p, w.tmpN.ptr, w.w1.ptr, s);
-    hipLaunchKernelGGL(max_abs<R>, RB(), RT(), 0, s, w.w1.as<C<R>>(), D, w.partials.as<double>(), (int)SLOT_MAX);
-    hipLaunchKernelGGL(gamma_from_max, dim3(1), RT(), 0, s, (const double *)w.partials.as<double>(), (int)SLOT_MAX,
+    VEC_LAUNCH(p, max_abs<R>, RB(), RT(), 0, s, w.w1.as<C<R>>(), D, w.partials.as<double>(), (int)SLOT_MAX);
+    VEC_LAUNCH(p, gamma_from_max, dim3(1), RT(), 0, s, (const double *)w.partials.as<double>(), (int)SLOT_MAX,
                        beta, w.scalars.as<double>());
     RIOP_HIP(hipGetLastError());
 }
 
+// Algorithm 1, steps 1-3 (or a resumed state), penalty and data in plan order.
 template <typename R>
-static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, void *x_inout,
-                     riop_sdmm_stats *stats, hipStream_t s) {
+static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, const void *x0,
+                      hipStream_t s) {
     ensure_work(p);
     SdmmWork &w = p->sd;
     const long N = (long)p->n * p->n, D = (long)p->q * N, M = (long)p->M;
     const size_t cb = cbytes(p);
-    double *part = w.partials.as<double>();
     double *sc = w.scalars.as<double>();
-    const int T = std::max(0, prm->T);
-    w.history.alloc(sizeof(double) * 4 * std::max(1, T));
+    w.hist_cap = std::max(1, prm->T);
+    w.history.alloc(sizeof(double) * 4 * w.hist_cap);
+    w.n_cg = prm->n_cg;
+    w.weights = prm->weights;
     C<R> *xh = w.xhat.as<C<R>>();
 
-    // Visibilities in plan order.
     if (M > 0)
-        hipLaunchKernelGGL(gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(y), p->perm.as<int>(),
-                           w.ysort.as<C<R>>(), M);
-    hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_EPS, eps);
-    // Penalty.
+        VEC_LAUNCH(p, gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(y), p->perm.as<int>(),
+                   w.ysort.as<C<R>>(), M);
+    VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_EPS, eps);
+    VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_ITER, 0.0);
     if (prm->gamma > 0) {
-        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_GAMMA, prm->gamma);
+        VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_GAMMA, prm->gamma);
     } else {
         gamma_run<R>(p, w.ysort.ptr, 0, prm->beta, s);
     }
-    RIOP_HIP(hipGetLastError());
-
     if (prm->resume) {
-        RIOP_REQUIRE(x_inout && prm->z1 && prm->z2 && prm->z3 && prm->rhs, RIOP_EINVAL,
-                     "resume needs x_inout, z1, z2, z3 and rhs");
-        RIOP_HIP(hipMemcpyAsync(xh, x_inout, cb * N, hipMemcpyDeviceToDevice, s));
+        RIOP_REQUIRE(x0 && prm->z1 && prm->z2 && prm->z3 && prm->rhs, RIOP_EINVAL,
+                     "resume needs x, z1, z2, z3 and rhs");
+        RIOP_HIP(hipMemcpyAsync(xh, x0, cb * N, hipMemcpyDeviceToDevice, s));
         RIOP_HIP(hipMemcpyAsync(w.z1loc.ptr, prm->z1, cb * D, hipMemcpyDeviceToDevice, s));
         RIOP_HIP(hipMemcpyAsync(w.z3loc.ptr, prm->z3, cb * N, hipMemcpyDeviceToDevice, s));
         RIOP_HIP(hipMemcpyAsync(w.rhs.ptr, prm->rhs, cb * N, hipMemcpyDeviceToDevice, s));
         if (M > 0)
-            hipLaunchKernelGGL(gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(prm->z2),
-                               p->perm.as<int>(), w.z2loc.as<C<R>>(), M);
-        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, prm->f1_prev);
+            VEC_LAUNCH(p, gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(prm->z2),
+                       p->perm.as<int>(), w.z2loc.as<C<R>>(), M);
+        VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, prm->f1_prev);
     } else {
-        // Algorithm 1 steps 1-3: z_i = 0, r_i = L_i x0, x_i = L_i^dagger r_i.
+        // z_i = 0, r_i = L_i x0, x_i = L_i^dagger r_i.
         launch_fill_zero<R>(w.z1loc.ptr, D, s);
         launch_fill_zero<R>(w.z2loc.ptr, std::max<long>(1, M), s);
         launch_fill_zero<R>(w.z3loc.ptr, N, s);
-        if (x_inout) {
-            RIOP_HIP(hipMemcpyAsync(xh, x_inout, cb * N, hipMemcpyDeviceToDevice, s));
+        if (x0) {
+            RIOP_HIP(hipMemcpyAsync(xh, x0, cb * N, hipMemcpyDeviceToDevice, s));
             launch_psi_adj<R>(p, xh, w.w1.ptr, s);
             launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
             gram_sorted<R>(p, xh, w.tmpN.ptr, s);
-            hipLaunchKernelGGL(add3<R>, RB(), RT(), 0, s, w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), (const C<R> *)xh,
-                               w.rhs.as<C<R>>(), N);
+            VEC_LAUNCH(p, add3<R>, RB(), RT(), 0, s, w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), (const C<R> *)xh,
+                       w.rhs.as<C<R>>(), N);
         } else {
             launch_fill_zero<R>(xh, N, s);
             launch_fill_zero<R>(w.rhs.ptr, N, s);
         }
-        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, 0.0);
+        VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, 0.0);
     }
     RIOP_HIP(hipGetLastError());
+    w.initialised = true;
+}
 
-    Prox1<R> px{w.z1loc.as<C<R>>(), w.w1.as<C<R>>(), static_cast<const R *>(prm->weights), sc + SC_GAMMA,
+// Enqueue `iters` iterations of Algorithm 1 (steps 5-9 and the halting
+// quantities).  No host synchronisation and no allocation: safe to capture
+// in a HIP graph and to replay.
+template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t s) {
+    SdmmWork &w = p->sd;
+    RIOP_REQUIRE(w.initialised, RIOP_EINVAL, "SDMM state not initialised");
+    const long N = (long)p->n * p->n, M = (long)p->M;
+    double *part = w.partials.as<double>();
+    double *sc = w.scalars.as<double>();
+    C<R> *xh = w.xhat.as<C<R>>();
+    Prox1<R> px{w.z1loc.as<C<R>>(), w.w1.as<C<R>>(), static_cast<const R *>(w.weights), sc + SC_GAMMA,
                 sc + SC_F1ACC};
-    std::vector<double> hist(4 * std::max(1, T), 0.0);
-    int iters = 0;
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < iters; ++t) {
         // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x.
         int rr_slot = SLOT_RR0;
-        cg_run<R>(p, w.rhs.ptr, xh, prm->n_cg, &rr_slot, s);
+        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
-        hipLaunchKernelGGL(set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1ACC, 0.0);
+        VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1ACC, 0.0);
         launch_psi_adj_prox<R>(p, xh, px, s);
         launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
         // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2).
         launch_phi_fft_forward<R>(p, xh, s);
         launch_degrid<R>(p, w.s2.ptr, 0, s);
-        if (M > 0) {
-            hipLaunchKernelGGL(prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
-                               w.ysort.as<C<R>>(), M, part);
-            hipLaunchKernelGGL(prox2_update<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
-                               w.ysort.as<C<R>>(), p->vis.as<C<R>>(), M, (const double *)part,
-                               (const double *)sc);
-        } else {
-            hipLaunchKernelGGL(prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
-                               w.ysort.as<C<R>>(), 0L, part);
-        }
+        VEC_LAUNCH(p, prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(), w.ysort.as<C<R>>(),
+                   M, part);
+        if (M > 0)
+            VEC_LAUNCH(p, prox2_update<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
+                       w.ysort.as<C<R>>(), p->vis.as<C<R>>(), M, (const double *)part, (const double *)sc);
         launch_grid<R>(p, p->vis.ptr, 0, s);
         launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
         // i = 3 and the next right-hand side.
-        hipLaunchKernelGGL(prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(),
-                           w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), w.rhs.as<C<R>>(), N);
-        hipLaunchKernelGGL(record_stats, dim3(1), RT(), 0, s, (const double *)part, sc, w.history.as<double>(), t,
-                           rr_slot);
+        VEC_LAUNCH(p, prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(), w.x1.as<C<R>>(),
+                   w.tmpN.as<C<R>>(), w.rhs.as<C<R>>(), N);
+        VEC_LAUNCH(p, record_stats, dim3(1), RT(), 0, s, (const double *)part, sc, w.history.as<double>(),
+                   w.hist_cap, rr_slot);
         RIOP_HIP(hipGetLastError());
-        iters = t + 1;
-        if (prm->early_stop) {
-            RIOP_HIP(hipMemcpyAsync(&hist[4 * t], w.history.as<double>() + 4 * t, 4 * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
-            RIOP_HIP(hipStreamSynchronize(s));
-            if (!std::isfinite(hist[4 * t + 2]))
-                throw Error{RIOP_ENONFINITE, "non-finite residual norm in SDMM"};
-            const double zeta = hist[4 * t + 1], nu = hist[4 * t + 2];
-            if (zeta < prm->xi && nu >= 1.0 - prm->tau && nu <= 1.0 + prm->tau) break;
-        }
     }
-    // Results.
-    if (x_inout) RIOP_HIP(hipMemcpyAsync(x_inout, xh, cb * N, hipMemcpyDeviceToDevice, s));
-    if (prm->z1) RIOP_HIP(hipMemcpyAsync(prm->z1, w.z1loc.ptr, cb * D, hipMemcpyDeviceToDevice, s));
-    if (prm->z3) RIOP_HIP(hipMemcpyAsync(prm->z3, w.z3loc.ptr, cb * N, hipMemcpyDeviceToDevice, s));
-    if (prm->rhs) RIOP_HIP(hipMemcpyAsync(prm->rhs, w.rhs.ptr, cb * N, hipMemcpyDeviceToDevice, s));
-    if (prm->z2 && M > 0)
-        hipLaunchKernelGGL(scatter_perm<R>, RB(), RT(), 0, s, (const C<R> *)w.z2loc.as<C<R>>(), p->perm.as<int>(),
-                           static_cast<C<R> *>(prm->z2), M);
+}
+
+// Copy the state out, read the statistics (synchronises).
+template <typename R>
+static void sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, riop_sdmm_stats *stats,
+                        double *history, hipStream_t s) {
+    SdmmWork &w = p->sd;
+    RIOP_REQUIRE(w.initialised, RIOP_EINVAL, "SDMM state not initialised");
+    const long N = (long)p->n * p->n, D = (long)p->q * N, M = (long)p->M;
+    const size_t cb = cbytes(p);
+    double *sc = w.scalars.as<double>();
+    if (x_out) RIOP_HIP(hipMemcpyAsync(x_out, w.xhat.ptr, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm && prm->z1) RIOP_HIP(hipMemcpyAsync(prm->z1, w.z1loc.ptr, cb * D, hipMemcpyDeviceToDevice, s));
+    if (prm && prm->z3) RIOP_HIP(hipMemcpyAsync(prm->z3, w.z3loc.ptr, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm && prm->rhs) RIOP_HIP(hipMemcpyAsync(prm->rhs, w.rhs.ptr, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm && prm->z2 && M > 0)
+        VEC_LAUNCH(p, scatter_perm<R>, RB(), RT(), 0, s, (const C<R> *)w.z2loc.as<C<R>>(), p->perm.as<int>(),
+                   static_cast<C<R> *>(prm->z2), M);
     double scal[kScalars] = {};
     RIOP_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, s));
-    if (iters > 0)
-        RIOP_HIP(hipMemcpyAsync(hist.data(), w.history.ptr, sizeof(double) * 4 * iters, hipMemcpyDeviceToHost, s));
     RIOP_HIP(hipStreamSynchronize(s));
-    if (prm->history) std::copy(hist.begin(), hist.begin() + 4 * iters, prm->history);
+    const int iters = (int)scal[SC_ITER];
+    const int kept = std::min(iters, w.hist_cap);
+    std::vector<double> hist(4 * (size_t)std::max(1, kept), 0.0);
+    if (kept > 0) {
+        RIOP_HIP(hipMemcpyAsync(hist.data(), w.history.ptr, sizeof(double) * 4 * kept, hipMemcpyDeviceToHost, s));
+        RIOP_HIP(hipStreamSynchronize(s));
+    }
+    if (history) std::copy(hist.begin(), hist.begin() + 4 * kept, history);
     if (stats) {
         stats->iters = iters;
         stats->gamma = scal[SC_GAMMA];
-        stats->f1 = iters ? hist[4 * (iters - 1)] : 0.0;
-        stats->zeta = iters ? hist[4 * (iters - 1) + 1] : INFINITY;
-        stats->nu = iters ? hist[4 * (iters - 1) + 2] : 0.0;
+        stats->f1 = kept ? hist[4 * (kept - 1)] : 0.0;
+        stats->zeta = kept ? hist[4 * (kept - 1) + 1] : INFINITY;
+        stats->nu = kept ? hist[4 * (kept - 1) + 2] : 0.0;
     }
-    for (int t = 0; t < iters; ++t)
+    for (int t = 0; t < kept; ++t)
         if (!std::isfinite(hist[4 * t]) || !std::isfinite(hist[4 * t + 2]))
             throw Error{RIOP_ENONFINITE, "non-finite value reached a norm in SDMM"};
+}
+
+template <typename R>
+static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, void *x_inout,
+                     riop_sdmm_stats *stats, hipStream_t s) {
+    sdmm_init<R>(p, y, eps, prm, x_inout, s);
+    const int T = std::max(0, prm->T);
+    if (!prm->early_stop) {
+        sdmm_step<R>(p, T, s);
+    } else {
+        double h[4];
+        for (int t = 0; t < T; ++t) {
+            sdmm_step<R>(p, 1, s);
+            RIOP_HIP(hipMemcpyAsync(h, p->sd.history.as<double>() + 4 * t, sizeof h, hipMemcpyDeviceToHost, s));
+            RIOP_HIP(hipStreamSynchronize(s));
+            if (!std::isfinite(h[2])) throw Error{RIOP_ENONFINITE, "non-finite residual norm in SDMM"};
+            if (h[1] < prm->xi && h[2] >= 1.0 - prm->tau && h[2] <= 1.0 + prm->tau) break;
+        }
+    }
+    sdmm_finish<R>(p, prm, x_inout, stats, prm->history, s);
 }
 
 template <typename R> static void apply_q_run(riop_plan *p, const void *x, void *out, hipStream_t s) {
     const long N = (long)p->n * p->n;
     ensure_work(p);
     gram_sorted<R>(p, x, p->sd.tmpN.ptr, s);
-    hipLaunchKernelGGL(add_2x<R>, RB(), RT(), 0, s, p->sd.tmpN.as<C<R>>(), static_cast<const C<R> *>(x),
+    VEC_LAUNCH(p, add_2x<R>, RB(), RT(), 0, s, p->sd.tmpN.as<C<R>>(), static_cast<const C<R> *>(x),
                        static_cast<C<R> *>(out), N);
     RIOP_HIP(hipGetLastError());
 }
@@ -471,7 +512,7 @@ template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x,
     int slot = SLOT_RR0;
     cg_run<R>(p, b, x, n_iter, &slot, s);
     if (rr_out) {
-        hipLaunchKernelGGL(slot_to_scalar, dim3(1), RT(), 0, s, (const double *)p->sd.partials.as<double>(), slot,
+        VEC_LAUNCH(p, slot_to_scalar, dim3(1), RT(), 0, s, (const double *)p->sd.partials.as<double>(), slot,
                            p->sd.scalars.as<double>(), (int)SC_RRFINAL);
         RIOP_HIP(hipGetLastError());
         RIOP_HIP(hipMemcpyAsync(rr_out, p->sd.scalars.as<double>() + SC_RRFINAL, sizeof(double),
@@ -560,6 +601,45 @@ riop_status riop_sdmm(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             sdmm_run<double>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
         else
             sdmm_run<float>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, const void *x0,
+                           void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(prm, RIOP_EINVAL, "params is NULL");
+        RIOP_REQUIRE(y || p->M == 0, RIOP_EINVAL, "y is NULL");
+        RIOP_REQUIRE(eps > 0 && std::isfinite(eps), RIOP_EINVAL, "eps must be positive and finite");
+        RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0, RIOP_EINVAL, "T and n_cg must be >= 0");
+        RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        if (p->prec == RIOP_F64)
+            sdmm_init<double>(p, y, eps, prm, x0, static_cast<hipStream_t>(stream));
+        else
+            sdmm_init<float>(p, y, eps, prm, x0, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm_step(riop_plan *p, int32_t iterations, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(iterations >= 0, RIOP_EINVAL, "iterations must be >= 0");
+        if (p->prec == RIOP_F64)
+            sdmm_step<double>(p, iterations, static_cast<hipStream_t>(stream));
+        else
+            sdmm_step<float>(p, iterations, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, riop_sdmm_stats *stats,
+                             void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        double *hist = prm ? prm->history : nullptr;
+        if (p->prec == RIOP_F64)
+            sdmm_finish<double>(p, prm, x_out, stats, hist, static_cast<hipStream_t>(stream));
+        else
+            sdmm_finish<float>(p, prm, x_out, stats, hist, static_cast<hipStream_t>(stream));
     });
 }
 

@@ -235,6 +235,40 @@ riop_status riop_sdmm_step(riop_plan *plan, int32_t iterations, void *stream);
 riop_status riop_sdmm_finish(riop_plan *plan, const riop_sdmm_params *params, void *x_out,
                              riop_sdmm_stats *stats, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched SDMM over channels of uneven sizes (many frequency channels or
+ * observations solved independently, each its own instance of Algorithm 1).
+ *
+ * riop_batch_create   one plan per channel: descs[c] and device uv[c] as for
+ *                     riop_plan_create.  autotune != 0 picks each channel's
+ *                     gridding tile by timing Phi / Phi^dagger pairs for every
+ *                     admissible tile (desc.tile is then ignored).  Synchronises.
+ * riop_batch_sdmm     run params->T iterations of every channel from x^(0) = 0.
+ *                     The iterations are captured once into a HIP graph (one
+ *                     branch per channel, default-priority streams owned by the
+ *                     batch) holding iters_per_graph iterations, and the graph is
+ *                     replayed; a remainder runs without the graph.  y[c] device
+ *                     M_c complex (caller order), eps[c] > 0, x_out[c] device
+ *                     n_c^2 complex (nullable array or entries), stats array of
+ *                     nchannels (nullable).  params: shared T, n_cg, gamma/beta;
+ *                     resume, early_stop, weights, state and history pointers
+ *                     must be zero.  Synchronises.
+ * riop_batch_plan     borrow channel c's plan (owned by the batch).
+ * riop_batch_tile     channel c's tile and the measured ms per pair for tiles
+ *                     8, 16, 32, 64 (negative where not tried or not tuned).
+ * riop_autotune_tile  the tile search alone for one description. */
+typedef struct riop_batch riop_batch;
+riop_status riop_batch_create(const riop_desc *descs, int32_t nchannels, const void *const *uv,
+                              int32_t autotune, void *stream, riop_batch **out);
+riop_status riop_batch_sdmm(riop_batch *batch, const void *const *y, const double *eps,
+                            const riop_sdmm_params *params, int32_t iters_per_graph,
+                            void *const *x_out, riop_sdmm_stats *stats, void *stream);
+riop_status riop_batch_plan(riop_batch *batch, int32_t channel, riop_plan **plan);
+riop_status riop_batch_tile(const riop_batch *batch, int32_t channel, int32_t *tile, double *pair_ms);
+riop_status riop_batch_destroy(riop_batch *batch);
+riop_status riop_autotune_tile(const riop_desc *desc, const void *uv, int32_t reps, void *stream,
+                               int32_t *best_tile, double *pair_ms);
+
 /* Kernel timing with HIP events (for benchmarks).  When enabled, every kernel
  * launch of the plan is bracketed by a pair of events recorded on the launch
  * stream and attributed to a kernel kind (see riop_timing_name).  Enabling

@@ -26,7 +26,8 @@ STATUS = {0: "RIOP_OK", -1: "RIOP_EINVAL", -2: "RIOP_ESHAPE", -3: "RIOP_ENOMEM",
 EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan_layout",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_gamma",
-           "riop_sdmm", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
+           "riop_sdmm", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
+           "riop_batch_destroy", "riop_autotune_tile", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
            "riop_timing_name", "riop_last_error", "riop_version")
 
 
@@ -90,6 +91,15 @@ def lib() -> ctypes.CDLL:
         L.riop_sdmm_init.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp, vp]
         L.riop_sdmm_step.argtypes = [vp, i32, vp]
         L.riop_sdmm_finish.argtypes = [vp, ctypes.POINTER(SdmmParams), vp, ctypes.POINTER(SdmmStats), vp]
+        L.riop_batch_create.argtypes = [ctypes.POINTER(Desc), i32, ctypes.POINTER(vp), i32, vp,
+                                        ctypes.POINTER(vp)]
+        L.riop_batch_sdmm.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(dbl), ctypes.POINTER(SdmmParams),
+                                      i32, ctypes.POINTER(vp), ctypes.POINTER(SdmmStats), vp]
+        L.riop_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.riop_batch_tile.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+        L.riop_batch_destroy.argtypes = [vp]
+        L.riop_autotune_tile.argtypes = [ctypes.POINTER(Desc), vp, i32, vp, ctypes.POINTER(i32),
+                                         ctypes.POINTER(dbl)]
         L.riop_timing_enable.argtypes = [vp, i32]
         L.riop_timing_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.riop_timing_kinds.argtypes = []
@@ -277,6 +287,100 @@ class Plan:
         state["f1_prev"] = st.f1 if st.iters else state["f1_prev"]
         stats = {k: getattr(st, k) for k, _ in SdmmStats._fields_}
         return x, stats, history, state
+
+
+class _BorrowedPlan(Plan):
+    """A channel plan owned by a Batch (not destroyed by Python)."""
+
+    def __init__(self, handle, n, M, J, levels, q, prec, device):
+        self._h = handle
+        self.prec = prec
+        self.rdtype = torch.float32 if prec == "f32" else torch.float64
+        self.cdtype = torch.complex64 if prec == "f32" else torch.complex128
+        self.device = device
+        self.n, self.M, self.J, self.levels, self.q = n, M, J, levels, q
+
+    def close(self):
+        self._h = ctypes.c_void_p()
+
+
+class Batch:
+    """Many channels of uneven sizes solved by SDMM in one replayed HIP graph.
+
+    channels: list of (n, uv tensor) with uv a (M_c, 2) real CUDA tensor.
+    """
+
+    def __init__(self, channels, J: int = 8, levels: int = 4, dict_mask: int = FULL_MASK,
+                 prec: str = "f32", autotune: bool = True, stream=None):
+        self.prec = prec
+        rd = torch.float32 if prec == "f32" else torch.float64
+        self.cdtype = torch.complex64 if prec == "f32" else torch.complex128
+        self.uv = [uv.contiguous() for _, uv in channels]
+        for uv in self.uv:
+            if uv.dtype != rd or not uv.is_cuda or uv.dim() != 2 or uv.shape[1] != 2:
+                raise ValueError(f"uv must be (M, 2) {rd} CUDA tensors")
+        self.device = self.uv[0].device
+        self.sizes = [(n, uv.shape[0]) for (n, _), uv in zip(channels, self.uv)]
+        nc = len(channels)
+        descs = (Desc * nc)(*[Desc(n=n, oversample=2, M=M, J=J, levels=levels, dict_mask=dict_mask,
+                                   prec=RIOP_F32 if prec == "f32" else RIOP_F64) for n, M in self.sizes])
+        uvp = (ctypes.c_void_p * nc)(*[uv.data_ptr() for uv in self.uv])
+        h = ctypes.c_void_p()
+        _check(lib().riop_batch_create(descs, nc, uvp, int(autotune), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        q = bin(dict_mask).count("1")
+        self.plans = []
+        for c, (n, M) in enumerate(self.sizes):
+            ph = ctypes.c_void_p()
+            _check(lib().riop_batch_plan(self._h, c, ctypes.byref(ph)))
+            self.plans.append(_BorrowedPlan(ph, n, M, J, levels, q, prec, self.device))
+
+    def tiles(self):
+        out = []
+        for c in range(len(self.sizes)):
+            t = ctypes.c_int32()
+            ms = (ctypes.c_double * 4)()
+            _check(lib().riop_batch_tile(self._h, c, ctypes.byref(t), ms))
+            out.append((t.value, list(ms)))
+        return out
+
+    def sdmm(self, ys, eps, T: int, n_cg: int = 16, gamma: float = 0.0, beta: float = 1e-3,
+             iters_per_graph: int = 10, stream=None):
+        nc = len(self.sizes)
+        ys = [y.contiguous() for y in ys]
+        xs = [torch.empty((n, n), dtype=self.cdtype, device=self.device) for n, _ in self.sizes]
+        yp = (ctypes.c_void_p * nc)(*[y.data_ptr() for y in ys])
+        xp = (ctypes.c_void_p * nc)(*[x.data_ptr() for x in xs])
+        ep = (ctypes.c_double * nc)(*[float(e) for e in eps])
+        st = (SdmmStats * nc)()
+        prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=1e-3, tau=0.1)
+        _check(lib().riop_batch_sdmm(self._h, yp, ep, ctypes.byref(prm), iters_per_graph, xp, st, _stream(stream)))
+        stats = [{k: getattr(s, k) for k, _ in SdmmStats._fields_} for s in st]
+        return xs, stats
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for p in self.plans:
+                p.close()
+            _check(lib().riop_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_tile(n: int, uv: torch.Tensor, J: int = 8, prec: str = "f32", reps: int = 3, stream=None):
+    """(best tile, ms per Phi/Phi^dagger pair for tiles 8, 16, 32, 64)."""
+    d = Desc(n=n, oversample=2, M=uv.shape[0], J=J, levels=1, dict_mask=1,
+             prec=RIOP_F32 if prec == "f32" else RIOP_F64)
+    t = ctypes.c_int32()
+    ms = (ctypes.c_double * 4)()
+    _check(lib().riop_autotune_tile(ctypes.byref(d), uv.contiguous().data_ptr(), reps, _stream(stream),
+                                    ctypes.byref(t), ms))
+    return t.value, list(ms)
 
 
 def noise_bound(M: int, sigma: float) -> float:

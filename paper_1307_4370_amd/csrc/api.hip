@@ -82,7 +82,7 @@ TimedScope::~TimedScope() {
 
 static const char *kKindNames[KK_COUNT] = {"fft_fwd_col", "fft_fwd_row", "fft_adj_row", "fft_adj_col",
                                            "degrid",      "grid",        "grid_zero",   "psi_adj",
-                                           "psi",         "vector"};
+                                           "psi",         "vector",      "gram"};
 
 // ---------------------------------------------------------------------------
 // Kaiser-Bessel kernel on the host.
@@ -411,6 +411,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         const size_t N = (size_t)p->n * p->n;
         p->tmp.alloc(cb * (size_t)p->K * p->n);
         p->grid.alloc(cb * (size_t)p->K * p->K);
+        p->grid2.alloc(cb * (size_t)p->K * p->K);
         p->vis.alloc(cb * (size_t)std::max<int64_t>(1, p->M));
         p->img.alloc(cb * N);
         size_t lls = 0;
@@ -420,7 +421,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         build_layout(p, uv, s);
         p->device_bytes = 0;
         for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->kcoef, &p->deapod,
-                                &p->fft.twiddle, &p->tmp, &p->grid, &p->vis, &p->img, &p->filters, &p->ll})
+                                &p->fft.twiddle, &p->tmp, &p->grid, &p->grid2, &p->vis, &p->img, &p->filters, &p->ll})
             p->device_bytes += (int64_t)b->bytes;
     });
     if (st != RIOP_OK) {

@@ -102,7 +102,7 @@ struct FftPlan {
 // Kernel kinds for event timing.
 enum KernelKind {
     KK_FFT_FWD_COL = 0, KK_FFT_FWD_ROW, KK_FFT_ADJ_ROW, KK_FFT_ADJ_COL,
-    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_COUNT
+    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_GRAM, KK_COUNT
 };
 
 struct Timing {
@@ -167,6 +167,7 @@ struct riop_plan {
     // Workspaces.
     riop::DevBuf tmp;    // K x n complex
     riop::DevBuf grid;   // K x K complex
+    riop::DevBuf grid2;  // K x K complex: output grid of the fused Gram kernel
     riop::DevBuf vis;    // M complex, plan order scratch
     riop::DevBuf img;    // n x n complex scratch
 
@@ -189,7 +190,11 @@ inline size_t rbytes(const riop_plan *p) { return p->prec == RIOP_F64 ? 8 : 4; }
 // Launch helpers implemented in the kernel translation units.  All take the
 // plan's real type as a template parameter and enqueue on `st`.
 template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st);
-template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st);
+// Adjoint FFT passes; `grid` selects the input grid (nullptr: the plan's grid).
+template <typename R>
+void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid = nullptr);
+// out_grid = G^T G in_grid (fused degrid + grid, the Gram part of Phi^dagger Phi).
+template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
 template <typename R>
 void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st);
 template <typename R>

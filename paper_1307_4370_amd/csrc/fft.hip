@@ -344,12 +344,12 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
     launch_pass<R, -1, false>(p, b, KK_FFT_FWD_ROW, st);
 }
 
-template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st) {
+template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid) {
     const int n = p->n, K = p->K;
     const R *d = p->deapod.as<R>();
     // Pass 1: rows k1 of grid, inverse transform over k2, keep the n cropped outputs.
     FftArgs<R> a{};
-    a.in = p->grid.as<C<R>>();
+    a.in = grid ? static_cast<const C<R> *>(grid) : p->grid.as<C<R>>();
     a.out = p->tmp.as<C<R>>();
     a.in_ts = K;
     a.in_es = 1;
@@ -383,7 +383,7 @@ template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStre
 
 template void launch_phi_fft_forward<float>(riop_plan *, const void *, hipStream_t);
 template void launch_phi_fft_forward<double>(riop_plan *, const void *, hipStream_t);
-template void launch_phi_fft_adjoint<float>(riop_plan *, void *, hipStream_t);
-template void launch_phi_fft_adjoint<double>(riop_plan *, void *, hipStream_t);
+template void launch_phi_fft_adjoint<float>(riop_plan *, void *, hipStream_t, const void *);
+template void launch_phi_fft_adjoint<double>(riop_plan *, void *, hipStream_t, const void *);
 
 }  // namespace riop

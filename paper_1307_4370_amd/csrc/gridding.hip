@@ -336,6 +336,85 @@ __global__ void __launch_bounds__(kDegridThreads) grid_kernel(GridArgs<R> a) {
     }
 }
 
+// Fused G^T G: each work unit stages its input region, and for each of its
+// visibilities computes the weights once, interpolates s = sum w X and spreads
+// s w back into an LDS accumulator; the accumulator is added into the output
+// grid (zeroed beforehand) with one global atomic per cell.
+template <typename R, int J>
+__device__ inline void gram_one(const GridArgs<R> &a, const C<R> *reg, R *acc_r, R *acc_i, int W, int ta, int tb,
+                                int v) {
+    const uint32_t cv = a.cell[v];
+    const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;
+    R wu_[J], wv_[J];
+    kb_weights<R, J>(a.frac[2 * (int64_t)v], a.kc, wu_);
+    kb_weights<R, J>(a.frac[2 * (int64_t)v + 1], a.kc, wv_);
+    R sr = 0, si = 0;
+    const C<R> *base = reg + la * W + lb;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        R rr = 0, ri = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const C<R> g = base[i * W + j];
+            rr += wv_[j] * g.x;
+            ri += wv_[j] * g.y;
+        }
+        sr += wu_[i] * rr;
+        si += wu_[i] * ri;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const int o = la * W + lb;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const R cr = wu_[i] * sr, ci = wu_[i] * si;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            atomicAdd(&acc_r[o + i * W + j], cr * wv_[j]);
+            atomicAdd(&acc_i[o + i * W + j], ci * wv_[j]);
+        }
+    }
+}
+
+template <typename R, int J>
+__global__ void __launch_bounds__(kDegridThreads) gram_kernel(GridArgs<R> a, const C<R> *__restrict__ gin) {
+    extern __shared__ unsigned char smem_raw[];
+    const WorkUnit wu = a.units[blockIdx.x];
+    const int W = a.T + J - 1;
+    C<R> *reg = reinterpret_cast<C<R> *>(smem_raw);
+    R *acc_r = reinterpret_cast<R *>(reg + W * W);
+    R *acc_i = acc_r + W * W;
+    const int ta = (wu.tile / a.tps) * a.T, tb = (wu.tile % a.tps) * a.T;
+    const int K = a.K;
+    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
+        const int i = idx / W, j = idx - (idx / W) * W;
+        int gi = ta + i, gj = tb + j;
+        if (gi >= K) gi -= K;
+        if (gj >= K) gj -= K;
+        reg[idx] = gin[(int64_t)gi * K + gj];
+        acc_r[idx] = 0;
+        acc_i[idx] = 0;
+    }
+    __syncthreads();
+    const int end = wu.start + wu.count;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int v = wu.start + threadIdx.x + k * kDegridThreads;
+        if (v < end) gram_one<R, J>(a, reg, acc_r, acc_i, W, ta, tb, v);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
+        const R vr = acc_r[idx], vi = acc_i[idx];
+        if (vr == R(0) && vi == R(0)) continue;
+        const int i = idx / W, j = idx - (idx / W) * W;
+        int gi = ta + i, gj = tb + j;
+        if (gi >= K) gi -= K;
+        if (gj >= K) gj -= K;
+        R *g = reinterpret_cast<R *>(a.grid + (int64_t)gi * K + gj);
+        unsafeAtomicAdd(g, vr);
+        unsafeAtomicAdd(g + 1, vi);
+    }
+}
+
 template <typename R> __global__ void fill_zero_kernel(C<R> *buf, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -504,6 +583,30 @@ template <typename R> void launch_grid(riop_plan *p, const void *y, int order_us
     RIOP_HIP(hipGetLastError());
 }
 
+template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st) {
+    {
+        TimedScope tz(p, KK_GRID_ZERO, st);
+        launch_fill_zero<R>(out_grid, (size_t)p->K * p->K, st);
+    }
+    if (p->nunits == 0) return;
+    GridArgs<R> a = grid_args<R>(p);
+    a.grid = static_cast<C<R> *>(out_grid);
+    const int W = p->tile + p->J - 1;
+    const size_t lds = (sizeof(C<R>) + 2 * sizeof(R)) * W * W;
+    const C<R> *gin = static_cast<const C<R> *>(in_grid);
+    TimedScope ts(p, KK_GRAM, st);
+    switch (p->J) {
+#define GR(JJ) \
+    case JJ: hipLaunchKernelGGL((gram_kernel<R, JJ>), dim3(p->nunits), dim3(kDegridThreads), lds, st, a, gin); break;
+        RIOP_J_CASES(GR)
+#undef GR
+        default: throw Error{RIOP_ENOTSUP, "unsupported kernel width"};
+    }
+    RIOP_HIP(hipGetLastError());
+}
+
+template void launch_gram<float>(riop_plan *, const void *, void *, hipStream_t);
+template void launch_gram<double>(riop_plan *, const void *, void *, hipStream_t);
 template void launch_degrid<float>(riop_plan *, void *, int, hipStream_t);
 template void launch_degrid<double>(riop_plan *, void *, int, hipStream_t);
 template void launch_grid<float>(riop_plan *, const void *, int, hipStream_t);

@@ -296,11 +296,10 @@ static void ensure_work(riop_plan *p) {
 }
 
 template <typename R> static void gram_sorted(riop_plan *p, const void *x, void *out, hipStream_t s) {
-    // out = Phi^dagger Phi x (plan order inside).
+    // out = Phi^dagger Phi x = Z^T D F^dagger (G^T G) F D Z x, with G^T G fused.
     launch_phi_fft_forward<R>(p, x, s);
-    launch_degrid<R>(p, p->vis.ptr, 0, s);
-    launch_grid<R>(p, p->vis.ptr, 0, s);
-    launch_phi_fft_adjoint<R>(p, out, s);
+    launch_gram<R>(p, p->grid.ptr, p->grid2.ptr, s);
+    launch_phi_fft_adjoint<R>(p, out, s, p->grid2.ptr);
 }
 
 template <typename R>

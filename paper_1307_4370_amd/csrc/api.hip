@@ -183,6 +183,19 @@ void build_kernel_tables(riop_plan *p) {
     for (int i = 0; i < n; ++i) d[i] = 1.0 / kb_phihat(i - n / 2, J, K, beta, i0b);
     const size_t rb = rbytes(p);
     p->kcoef_host = coef;
+    // Compact copy [pair][even/odd][D/2 + 1] for kernels that stage it in LDS.
+    const int KS = D / 2 + 1;
+    std::vector<double> compact((size_t)(J / 2) * 2 * KS, 0.0);
+    for (int jp = 0; jp < J / 2; ++jp)
+        for (int e = 0; e < 2; ++e)
+            for (int k = 0; k < KS; ++k) compact[(size_t)(jp * 2 + e) * KS + k] = coef[(size_t)(jp * 2 + e) * kMaxPoly + k];
+    p->kcoef_owner.alloc(rb * compact.size());
+    if (p->prec == RIOP_F64) {
+        RIOP_HIP(hipMemcpy(p->kcoef_owner.ptr, compact.data(), rb * compact.size(), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> c32(compact.begin(), compact.end());
+        RIOP_HIP(hipMemcpy(p->kcoef_owner.ptr, c32.data(), rb * c32.size(), hipMemcpyHostToDevice));
+    }
     p->kcoef.alloc(rb * coef.size());
     p->deapod.alloc(rb * n);
     if (p->prec == RIOP_F64) {
@@ -318,7 +331,11 @@ void build_filters(riop_plan *p) {
     }
 }
 
-static int default_tile(int K) { return K >= 256 ? 32 : (K >= 64 ? 16 : 8); }
+static int default_tile(int K, int J) {
+    int t = K >= 256 ? 32 : (K >= 64 ? 16 : 8);
+    while (t < J) t *= 2;
+    return t;
+}
 
 static void validate(const riop_desc *d) {
     RIOP_REQUIRE(d, RIOP_EINVAL, "desc is NULL");
@@ -399,7 +416,10 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         for (int b = 0; b < 9; ++b)
             if (p->mask >> b & 1) p->bases[p->q++] = b;
         p->scale_q = 1.0 / std::sqrt((double)p->q);
-        p->tile = desc->tile ? desc->tile : default_tile(p->K);
+        p->tile = desc->tile ? desc->tile : default_tile(p->K, p->J);
+        RIOP_REQUIRE(p->tile >= p->J && p->K % p->tile == 0, RIOP_EINVAL,
+                     "gridding tile must be at least J and divide 2n");
+        p->owner = std::min(p->tile, p->prec == RIOP_F64 ? 16 : 32);
         p->tiles_per_side = p->K / p->tile;
         p->ntiles = p->tiles_per_side * p->tiles_per_side;
         RIOP_REQUIRE(p->ntiles <= 16384, RIOP_ENOTSUP, "too many gridding tiles; use a larger tile");
@@ -420,7 +440,8 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         p->ll.alloc(cb * p->ll_stride * 8);
         build_layout(p, uv, s);
         p->device_bytes = 0;
-        for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->kcoef, &p->deapod,
+        for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->cell_start,
+                                &p->owner_order, &p->kcoef, &p->kcoef_owner, &p->deapod,
                                 &p->fft.twiddle, &p->tmp, &p->grid, &p->grid2, &p->vis, &p->img, &p->filters, &p->ll})
             p->device_bytes += (int64_t)b->bytes;
     });

@@ -144,11 +144,14 @@ struct riop_plan {
 
     // Visibility layout (plan order).
     int tile = 0, tiles_per_side = 0, ntiles = 0;
+    int owner = 0, nowner = 0;  // gridding owner tile side (divides tile) and count
     riop::DevBuf perm;        // int32[M]
     riop::DevBuf cell;        // uint32[M]: a0 | b0 << 16
     riop::DevBuf frac;        // R[2M]: (rho_u, rho_v)
     riop::DevBuf tile_start;  // int32[ntiles + 1]
-    riop::DevBuf units;       // WorkUnit[nunits]
+    riop::DevBuf units;       // WorkUnit[nunits] (degridding)
+    riop::DevBuf cell_start;  // int32[K^2 + 1]: plan-order start of each cell key
+    riop::DevBuf owner_order; // int32[ntiles]: gridding tiles, heaviest first
     int nunits = 0;
     int max_unit = 0;
 
@@ -159,6 +162,7 @@ struct riop_plan {
     double kfit_err = 0;
     riop::DevBuf kcoef;          // R[J/2][2][kMaxPoly]
     std::vector<double> kcoef_host;  // same table on the host, double
+    riop::DevBuf kcoef_owner;    // R[J/2][2][D/2 + 1] compact copy
     riop::DevBuf deapod;         // R[n]: d(p - n/2)
 
     // FFT.

@@ -4,15 +4,25 @@
 // Plan layout (built here, once per coverage): every visibility's first window
 // cell (a0, b0) = (floor(g - J/2) + 1) mod K and fractional offset
 // rho = g - J/2 - floor(g - J/2) in [0, 1), with g = u K / (2 pi) computed in
-// double precision, binned by the T x T grid tile holding (a0, b0) with a
-// stable counting sort (tile, then caller index).
+// double precision.  Visibilities are sorted by T x T grid tile, then by cell
+// inside the tile (row-major), then by caller index; cell_start[key] gives the
+// plan-order range of every cell (key = tile * T^2 + local row * T + local col).
 //
 // Degridding (G): one workgroup per work unit (a tile and a chunk of its
 // visibilities) stages the (T + J - 1)^2 grid region its windows can touch in
 // LDS, then each thread interpolates one visibility at a time from LDS.
-// Gridding (G^T): the same work units accumulate their visibilities' J x J
-// contributions into an LDS copy of the region with LDS atomics, then add the
-// region into the grid with one global atomic per cell.
+// Neighbouring threads hold neighbouring cells, which keeps LDS bank conflicts
+// low.
+//
+// Gridding (G^T), owner computes: one workgroup per output tile.  It walks the
+// visibilities whose windows reach the tile (its own tile and the last J - 1
+// rows / columns of the three neighbours above and to the left, found through
+// cell_start), stages their weights in LDS, and each wavefront adds runs of
+// same-cell visibilities, one lane per window cell, into its private copy of
+// the tile with plain read-modify-write (no atomics: floating-point LDS
+// atomics are slow on this GPU).  The private copies are summed in a fixed
+// order and the tile is written once with plain stores: no zeroing, no global
+// atomics, and a reproducible result.
 //
 // Kernel weights: for tap j the weight phi(rho + J/2 - 1 - j) is a polynomial
 // in s = 2 rho - 1 fitted at plan time; phi is even, so taps j and J-1-j share
@@ -33,7 +43,7 @@ template <> struct KDeg<double> { static constexpr int D = 14; };
 
 template <typename R>
 __global__ void bin_kernel(const R *__restrict__ uv, int64_t M, int K, int J, int T, int tps,
-                           double gscale, int *__restrict__ tile_of, uint32_t *__restrict__ cell_of,
+                           double gscale, int *__restrict__ key_of, uint32_t *__restrict__ cell_of,
                            R *__restrict__ frac_of, int *__restrict__ flag) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -41,7 +51,7 @@ __global__ void bin_kernel(const R *__restrict__ uv, int64_t M, int K, int J, in
     const double lim = M_PI * (1.0 + 9.5367431640625e-07);
     if (!(fabs(u) <= lim) || !(fabs(v) <= lim)) {  // also catches NaN
         atomicOr(flag, 1);
-        tile_of[m] = 0;
+        key_of[m] = 0;
         cell_of[m] = 0;
         frac_of[2 * m] = 0;
         frac_of[2 * m + 1] = 0;
@@ -52,24 +62,16 @@ __global__ void bin_kernel(const R *__restrict__ uv, int64_t M, int K, int J, in
     int a0 = ((int)fu + 1) % K, b0 = ((int)fv + 1) % K;
     if (a0 < 0) a0 += K;
     if (b0 < 0) b0 += K;
-    tile_of[m] = (a0 / T) * tps + (b0 / T);
+    const int tile = (a0 / T) * tps + (b0 / T);
+    key_of[m] = tile * T * T + (a0 % T) * T + (b0 % T);
     cell_of[m] = (uint32_t)a0 | ((uint32_t)b0 << 16);
     frac_of[2 * m] = (R)(hu - fu);
     frac_of[2 * m + 1] = (R)(hv - fv);
 }
 
-constexpr int kBinChunk = 16384;  // visibilities per binning block
-
-__global__ void hist_kernel(const int *__restrict__ tile_of, int64_t M, int ntiles, int nblk,
-                            int *__restrict__ counts) {
-    extern __shared__ int hist[];
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * kBinChunk;
-    const int64_t hi = min<int64_t>(M, lo + kBinChunk);
-    for (int64_t m = lo + threadIdx.x; m < hi; m += blockDim.x) atomicAdd(&hist[tile_of[m]], 1);
-    __syncthreads();
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) counts[(int64_t)t * nblk + blockIdx.x] = hist[t];
+__global__ void count_kernel(const int *__restrict__ key_of, int64_t M, int *__restrict__ counts) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M) atomicAdd(&counts[key_of[m]], 1);
 }
 
 // Exclusive scan of int32 in three launches (block scan, scan of block sums, add).
@@ -131,50 +133,50 @@ __global__ void scan_add(int *__restrict__ out, int64_t n, const int *__restrict
         if (base + i < n) out[base + i] += add;
 }
 
-__global__ void tile_start_kernel(const int *__restrict__ offsets, int ntiles, int nblk, int64_t M,
-                                  int *__restrict__ tile_start) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < ntiles) tile_start[t] = offsets[(int64_t)t * nblk];
-    if (t == ntiles) tile_start[t] = (int)M;
+__global__ void set_int(int *__restrict__ p, int64_t idx, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[idx] = v;
 }
 
-// Stable scatter: one wavefront per binning block walks its chunk in order,
-// ranking equal tiles among the 64 lanes of each step.
-template <typename R>
-__global__ void __launch_bounds__(64) scatter_kernel(const int *__restrict__ tile_of,
-                                                     const uint32_t *__restrict__ cell_of,
-                                                     const R *__restrict__ frac_of, int64_t M,
-                                                     int ntiles, int nblk,
-                                                     const int *__restrict__ offsets,
-                                                     int *__restrict__ perm, uint32_t *__restrict__ cell,
-                                                     R *__restrict__ frac) {
-    extern __shared__ int cursor[];
-    for (int t = threadIdx.x; t < ntiles; t += 64) cursor[t] = offsets[(int64_t)t * nblk + blockIdx.x];
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * kBinChunk;
-    const int64_t hi = min<int64_t>(M, lo + kBinChunk);
-    const int lane = threadIdx.x;
-    for (int64_t s = lo; s < hi; s += 64) {
-        const int64_t m = s + lane;
-        const int t = m < hi ? tile_of[m] : -1;
-        int before = 0, after = 0;
-        for (int l = 0; l < 64; ++l) {
-            const int tl = __shfl(t, l, 64);
-            before += (l < lane && tl == t) ? 1 : 0;
-            after += (l > lane && tl == t) ? 1 : 0;
+// Scatter by key (order inside a key is fixed afterwards by key_sort).
+__global__ void scatter_by_key(const int *__restrict__ key_of, int64_t M, const int *__restrict__ start,
+                               int *__restrict__ cursor, int *__restrict__ perm) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int k = key_of[m];
+    perm[start[k] + atomicAdd(&cursor[k], 1)] = (int)m;
+}
+
+// Stable order inside each key: insertion sort of the (few) caller indices.
+__global__ void key_sort(const int *__restrict__ start, int64_t nkeys, int *__restrict__ perm) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nkeys) return;
+    const int lo = start[k], hi = start[k + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        const int v = perm[i];
+        int j = i - 1;
+        while (j >= lo && perm[j] > v) {
+            perm[j + 1] = perm[j];
+            --j;
         }
-        int pos = 0;
-        if (t >= 0) pos = cursor[t] + before;
-        __syncthreads();
-        if (t >= 0) {
-            if (after == 0) cursor[t] = pos + 1;
-            perm[pos] = (int)m;
-            cell[pos] = cell_of[m];
-            frac[2 * (int64_t)pos] = frac_of[2 * m];
-            frac[2 * (int64_t)pos + 1] = frac_of[2 * m + 1];
-        }
-        __syncthreads();
+        perm[j + 1] = v;
     }
+}
+
+template <typename R>
+__global__ void gather_layout(const int *__restrict__ perm, const uint32_t *__restrict__ cell_of,
+                              const R *__restrict__ frac_of, int64_t M, uint32_t *__restrict__ cell,
+                              R *__restrict__ frac) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int m = perm[i];
+    cell[i] = cell_of[m];
+    frac[2 * i] = frac_of[2 * (int64_t)m];
+    frac[2 * i + 1] = frac_of[2 * (int64_t)m + 1];
+}
+
+__global__ void tile_start_from_keys(const int *__restrict__ start, int ntiles, int T2, int *__restrict__ ts) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= ntiles) ts[t] = start[(int64_t)t * T2];
 }
 
 // ---------------------------------------------------------------------------
@@ -197,6 +199,28 @@ __device__ inline void kb_weights(R rho, const KCoef<R> &kc, R (&w)[J]) {
     for (int jp = 0; jp < J / 2; ++jp) {
         const R *ce = kc.c[jp][0];
         const R *co = kc.c[jp][1];
+        R e = ce[NEV - 1];
+#pragma unroll
+        for (int k = NEV - 2; k >= 0; --k) e = e * u + ce[k];
+        R o = co[NOD - 1];
+#pragma unroll
+        for (int k = NOD - 2; k >= 0; --k) o = o * u + co[k];
+        w[jp] = e + s * o;
+        w[J - 1 - jp] = e - s * o;
+    }
+}
+
+// Same weights with the coefficient table in LDS, laid out [pair][even/odd][KS].
+template <typename R, int J>
+__device__ inline void kb_weights_lds(R rho, const R *kc, R (&w)[J]) {
+    constexpr int D = KDeg<R>::D;
+    constexpr int NEV = D / 2 + 1, NOD = (D + 1) / 2, KS = D / 2 + 1;
+    const R s = R(2) * rho - R(1);
+    const R u = s * s;
+#pragma unroll
+    for (int jp = 0; jp < J / 2; ++jp) {
+        const R *ce = kc + (jp * 2 + 0) * KS;
+        const R *co = kc + (jp * 2 + 1) * KS;
         R e = ce[NEV - 1];
 #pragma unroll
         for (int k = NEV - 2; k >= 0; --k) e = e * u + ce[k];
@@ -282,136 +306,155 @@ __global__ void __launch_bounds__(kDegridThreads) degrid_kernel(GridArgs<R> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gridding, owner computes.
+
+constexpr int kOwnThreads = 256;  // 4 wavefronts
+constexpr int kOwnWaves = kOwnThreads / 64;
+
+template <typename R> struct OwnerArgs {
+    C<R> *grid;               // output grid: every owned cell is written
+    const uint32_t *cell;     // plan order: a0 | b0 << 16
+    const R *frac;            // plan order: rho_u, rho_v
+    const int *perm;          // plan order -> caller order
+    const int *cell_start;    // K^2 + 1 plan-order offsets of the cell keys
+    const int *order;         // owner tiles, heaviest first
+    const C<R> *vin;          // values to grid
+    const R *kc;              // kernel coefficients [pair][even/odd][D/2 + 1]
+    int K, T, tps;            // grid side, sort tile side, sort tiles per side
+    int O, ops;               // owner tile side (divides T), owner tiles per side
+    int stage;                // visibilities staged per chunk
+};
+
+// Lane (i, j) of a wavefront covers window cells (i + 8p, j + 8q), p, q < NB.
 template <typename R, int J, bool USER>
-__device__ inline void grid_one(const GridArgs<R> &a, R *acc_r, R *acc_i, int W, int ta, int tb, int v) {
-    const uint32_t cv = a.cell[v];
-    const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;
-    R wu_[J], wv_[J];
-    kb_weights<R, J>(a.frac[2 * (int64_t)v], a.kc, wu_);
-    kb_weights<R, J>(a.frac[2 * (int64_t)v + 1], a.kc, wv_);
-    const C<R> val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
-    const int base = la * W + lb;
-#pragma unroll
-    for (int i = 0; i < J; ++i) {
-        const R cr = wu_[i] * val.x, ci = wu_[i] * val.y;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            atomicAdd(&acc_r[base + i * W + j], cr * wv_[j]);
-            atomicAdd(&acc_i[base + i * W + j], ci * wv_[j]);
-        }
-    }
-}
-
-template <typename R, int J, bool USER>
-__global__ void __launch_bounds__(kDegridThreads) grid_kernel(GridArgs<R> a) {
+__global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
+    constexpr int NB = (J + 7) / 8;
     extern __shared__ unsigned char smem_raw[];
-    const WorkUnit wu = a.units[blockIdx.x];
-    const int W = a.T + J - 1;
-    R *acc_r = reinterpret_cast<R *>(smem_raw);
-    R *acc_i = acc_r + W * W;
-    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-        acc_r[idx] = 0;
-        acc_i[idx] = 0;
-    }
-    __syncthreads();
-    const int ta = (wu.tile / a.tps) * a.T, tb = (wu.tile % a.tps) * a.T;
-    const int end = wu.start + wu.count;
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        const int v = wu.start + threadIdx.x + k * kDegridThreads;
-        if (v < end) grid_one<R, J, USER>(a, acc_r, acc_i, W, ta, tb, v);
-    }
-    __syncthreads();
-    const int K = a.K;
-    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-        const R vr = acc_r[idx], vi = acc_i[idx];
-        if (vr == R(0) && vi == R(0)) continue;
-        const int i = idx / W, j = idx - (idx / W) * W;
-        int gi = ta + i, gj = tb + j;
-        if (gi >= K) gi -= K;
-        if (gj >= K) gj -= K;
-        R *g = reinterpret_cast<R *>(a.grid + (int64_t)gi * K + gj);
-        unsafeAtomicAdd(g, vr);
-        unsafeAtomicAdd(g + 1, vi);
-    }
-}
+    const int T = a.T, K = a.K, tps = a.tps, S = a.stage, O = a.O, O2 = O * O;
+    const int NR = O + J - 1, NS = 2 * NR;
+    // LDS layout.
+    C<R> *priv = reinterpret_cast<C<R> *>(smem_raw);             // [waves][O*O]
+    C<R> *wuv = priv + kOwnWaves * O2;                           // [S][J]: wu_i * value
+    R *wvs = reinterpret_cast<R *>(wuv + (size_t)S * J);         // [S][J]
+    int *spos = reinterpret_cast<int *>(wvs + (size_t)S * J);    // [S]: (la + J) << 8 | (lb + J)
+    int *segbeg = spos + S;                                      // [NS]
+    int *segoff = segbeg + NS;                                   // [NS + 1]
+    constexpr int KS = KDeg<R>::D / 2 + 1;
+    R *kcl = reinterpret_cast<R *>(segoff + NS + 1 + ((NS + 1) & 1));  // [J/2][2][KS], 8-byte aligned
+    for (int i = threadIdx.x; i < (J / 2) * 2 * KS; i += blockDim.x) kcl[i] = a.kc[i];
 
-// Fused G^T G: each work unit stages its input region, and for each of its
-// visibilities computes the weights once, interpolates s = sum w X and spreads
-// s w back into an LDS accumulator; the accumulator is added into the output
-// grid (zeroed beforehand) with one global atomic per cell.
-template <typename R, int J>
-__device__ inline void gram_one(const GridArgs<R> &a, const C<R> *reg, R *acc_r, R *acc_i, int W, int ta, int tb,
-                                int v) {
-    const uint32_t cv = a.cell[v];
-    const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;
-    R wu_[J], wv_[J];
-    kb_weights<R, J>(a.frac[2 * (int64_t)v], a.kc, wu_);
-    kb_weights<R, J>(a.frac[2 * (int64_t)v + 1], a.kc, wv_);
-    R sr = 0, si = 0;
-    const C<R> *base = reg + la * W + lb;
-#pragma unroll
-    for (int i = 0; i < J; ++i) {
-        R rr = 0, ri = 0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const C<R> g = base[i * W + j];
-            rr += wv_[j] * g.x;
-            ri += wv_[j] * g.y;
-        }
-        sr += wu_[i] * rr;
-        si += wu_[i] * ri;
-        __builtin_amdgcn_sched_barrier(0);
+    const int ot = a.order[blockIdx.x];
+    const int oa = (ot / a.ops) * O, ob = (ot % a.ops) * O;
+    // Extended region: base-cell rows oa - (J-1) .. oa + O - 1 and columns
+    // ob - (J-1) .. ob + O - 1 (mod K).  Each row is split at the sort-tile
+    // boundary into at most two key-contiguous pieces.
+    const int cs = (ob - (J - 1) + K) % K;
+    const int tc0 = cs / T, lc0 = cs % T;
+    const int len0 = min(NR, T - lc0), len1 = NR - len0, tc1 = (tc0 + 1) % tps;
+    for (int sgi = threadIdx.x; sgi < NS; sgi += blockDim.x) {
+        const int r = sgi >> 1, piece = sgi & 1;
+        const int ar = (oa - (J - 1) + r + K) % K;
+        const int tr = ar / T, lr = ar % T;
+        const int64_t k0 = (int64_t)(tr * tps + (piece ? tc1 : tc0)) * T * T + lr * T + (piece ? 0 : lc0);
+        const int b = a.cell_start[k0];
+        segbeg[sgi] = b;
+        segoff[sgi + 1] = a.cell_start[k0 + (piece ? len1 : len0)] - b;
     }
-    const int o = la * W + lb;
-#pragma unroll
-    for (int i = 0; i < J; ++i) {
-        const R cr = wu_[i] * sr, ci = wu_[i] * si;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            atomicAdd(&acc_r[o + i * W + j], cr * wv_[j]);
-            atomicAdd(&acc_i[o + i * W + j], ci * wv_[j]);
-        }
+    for (int c = threadIdx.x; c < kOwnWaves * O2; c += blockDim.x) priv[c] = mk<R>(0, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        segoff[0] = 0;
+        for (int k = 0; k < NS; ++k) segoff[k + 1] += segoff[k];
     }
-}
+    __syncthreads();
+    const int total = segoff[NS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane >> 3, lj = lane & 7;
+    C<R> *mine = priv + wave * O2;
 
-template <typename R, int J>
-__global__ void __launch_bounds__(kDegridThreads) gram_kernel(GridArgs<R> a, const C<R> *__restrict__ gin) {
-    extern __shared__ unsigned char smem_raw[];
-    const WorkUnit wu = a.units[blockIdx.x];
-    const int W = a.T + J - 1;
-    C<R> *reg = reinterpret_cast<C<R> *>(smem_raw);
-    R *acc_r = reinterpret_cast<R *>(reg + W * W);
-    R *acc_i = acc_r + W * W;
-    const int ta = (wu.tile / a.tps) * a.T, tb = (wu.tile % a.tps) * a.T;
-    const int K = a.K;
-    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-        const int i = idx / W, j = idx - (idx / W) * W;
-        int gi = ta + i, gj = tb + j;
-        if (gi >= K) gi -= K;
-        if (gj >= K) gj -= K;
-        reg[idx] = gin[(int64_t)gi * K + gj];
-        acc_r[idx] = 0;
-        acc_i[idx] = 0;
-    }
-    __syncthreads();
-    const int end = wu.start + wu.count;
+    for (int chunk = 0; chunk < total; chunk += S) {
+        const int cnt = min(S, total - chunk);
+        // Phase 1: one visibility per thread -> weights and value into LDS.
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int f = chunk + t;
+            int lo = 0, hi = NS;  // segoff[lo] <= f < segoff[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (segoff[mid] <= f) lo = mid; else hi = mid;
+            }
+            const int v = segbeg[lo] + (f - segoff[lo]);
+            const int r = lo >> 1, piece = lo & 1;
+            const uint32_t cv = a.cell[v];
+            const int la = r - (J - 1);
+            const int lb = (int)(cv >> 16) % T + (piece ? len0 : -lc0) - (J - 1);
+            R wu_[J], wv_[J];
+            kb_weights_lds<R, J>(a.frac[2 * (int64_t)v], kcl, wu_);
+            kb_weights_lds<R, J>(a.frac[2 * (int64_t)v + 1], kcl, wv_);
+            const C<R> val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        const int v = wu.start + threadIdx.x + k * kDegridThreads;
-        if (v < end) gram_one<R, J>(a, reg, acc_r, acc_i, W, ta, tb, v);
+            for (int i = 0; i < J; ++i) {
+                wuv[t * J + i] = mk<R>(wu_[i] * val.x, wu_[i] * val.y);
+                wvs[t * J + i] = wv_[i];
+            }
+            spos[t] = ((la + J) << 8) | (lb + J);
+        }
+        __syncthreads();
+        // Phase 2: one staged visibility per step for each wavefront; runs of
+        // equal cells are summed in registers and added to the wave's copy.
+        const int per = (cnt + kOwnWaves - 1) / kOwnWaves;
+        const int e0 = wave * per, e1 = min(cnt, e0 + per);
+        if (e0 < e1) {
+            C<R> acc[NB][NB];
+#pragma unroll
+            for (int p = 0; p < NB; ++p)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[p][q] = mk<R>(0, 0);
+            int cur = spos[e0];
+            auto flush = [&](int pos) {
+                const int la = (pos >> 8) - J, lb = (pos & 255) - J;
+#pragma unroll
+                for (int p = 0; p < NB; ++p)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) {
+                        const int i = li + 8 * p, j = lj + 8 * q;
+                        const int ra = la + i, rb = lb + j;
+                        if (i < J && j < J && ra >= 0 && ra < O && rb >= 0 && rb < O) {
+                            C<R> g = mine[ra * O + rb];
+                            g.x += acc[p][q].x;
+                            g.y += acc[p][q].y;
+                            mine[ra * O + rb] = g;
+                        }
+                        acc[p][q] = mk<R>(0, 0);
+                    }
+            };
+            for (int e = e0; e < e1; ++e) {
+                const int pos = spos[e];
+                if (pos != cur) {
+                    flush(cur);
+                    cur = pos;
+                }
+#pragma unroll
+                for (int p = 0; p < NB; ++p)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) {
+                        const int i = li + 8 * p, j = lj + 8 * q;
+                        if (i < J && j < J) {
+                            const C<R> u = wuv[e * J + i];
+                            const R w = wvs[e * J + j];
+                            acc[p][q].x += u.x * w;
+                            acc[p][q].y += u.y * w;
+                        }
+                    }
+            }
+            flush(cur);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-        const R vr = acc_r[idx], vi = acc_i[idx];
-        if (vr == R(0) && vi == R(0)) continue;
-        const int i = idx / W, j = idx - (idx / W) * W;
-        int gi = ta + i, gj = tb + j;
-        if (gi >= K) gi -= K;
-        if (gj >= K) gj -= K;
-        R *g = reinterpret_cast<R *>(a.grid + (int64_t)gi * K + gj);
-        unsafeAtomicAdd(g, vr);
-        unsafeAtomicAdd(g + 1, vi);
+    // Sum the private copies in wave order and store the tile.
+    for (int c = threadIdx.x; c < O2; c += blockDim.x) {
+        C<R> sum = priv[c];
+        for (int w = 1; w < kOwnWaves; ++w) sum = cadd<R>(sum, priv[w * O2 + c]);
+        a.grid[(int64_t)(oa + c / O) * K + ob + c % O] = sum;
     }
 }
 
@@ -435,64 +478,69 @@ template <typename R> void launch_fill_zero(void *buf, size_t n, hipStream_t st)
 
 template <typename R> static void build_layout_t(riop_plan *p, const void *uv, hipStream_t st) {
     const int64_t M = p->M;
-    const int K = p->K, T = p->tile, tps = p->tiles_per_side, ntiles = p->ntiles;
+    const int K = p->K, T = p->tile, tps = p->tiles_per_side, ntiles = p->ntiles, J = p->J;
+    const int64_t nkeys = (int64_t)K * K;
     p->perm.alloc(sizeof(int32_t) * M);
     p->cell.alloc(sizeof(uint32_t) * M);
     p->frac.alloc(sizeof(R) * 2 * M);
     p->tile_start.alloc(sizeof(int32_t) * (ntiles + 1));
-    DevBuf tile_of, cell_of, frac_of, flag, counts, offsets, sums;
-    const int nblk = (int)std::max<int64_t>(1, (M + kBinChunk - 1) / kBinChunk);
-    const int64_t ncounts = (int64_t)ntiles * nblk;
-    tile_of.alloc(sizeof(int) * M);
+    p->cell_start.alloc(sizeof(int32_t) * (nkeys + 1));
+    DevBuf key_of, cell_of, frac_of, flag, counts, sums;
+    key_of.alloc(sizeof(int) * M);
     cell_of.alloc(sizeof(uint32_t) * M);
     frac_of.alloc(sizeof(R) * 2 * M);
     flag.alloc(sizeof(int));
-    counts.alloc(sizeof(int) * ncounts);
-    offsets.alloc(sizeof(int) * ncounts);
+    counts.alloc(sizeof(int) * nkeys);
     const int64_t per_blk = (int64_t)kScanBlock * kScanPer;
-    const int nsums = (int)((ncounts + per_blk - 1) / per_blk);
+    const int nsums = (int)((nkeys + per_blk - 1) / per_blk);
     sums.alloc(sizeof(int) * nsums);
     RIOP_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), st));
+    RIOP_HIP(hipMemsetAsync(counts.ptr, 0, sizeof(int) * nkeys, st));
+    const int threads = 256;
+    const unsigned gM = (unsigned)std::max<int64_t>(1, (M + threads - 1) / threads);
+    int *start = p->cell_start.as<int>();
     if (M > 0) {
-        const int threads = 256;
-        hipLaunchKernelGGL(bin_kernel<R>, dim3((unsigned)((M + threads - 1) / threads)), dim3(threads), 0, st,
-                           static_cast<const R *>(uv), M, K, p->J, T, tps, (double)K / (2.0 * M_PI),
-                           tile_of.as<int>(), cell_of.as<uint32_t>(), frac_of.as<R>(), flag.as<int>());
+        hipLaunchKernelGGL(bin_kernel<R>, dim3(gM), dim3(threads), 0, st, static_cast<const R *>(uv), M, K, J, T, tps,
+                           (double)K / (2.0 * M_PI), key_of.as<int>(), cell_of.as<uint32_t>(), frac_of.as<R>(),
+                           flag.as<int>());
+        hipLaunchKernelGGL(count_kernel, dim3(gM), dim3(threads), 0, st, key_of.as<int>(), M, counts.as<int>());
         RIOP_HIP(hipGetLastError());
     }
-    const size_t lds_tiles = sizeof(int) * ntiles;
-    hipLaunchKernelGGL(hist_kernel, dim3(nblk), dim3(256), lds_tiles, st, tile_of.as<int>(), M, ntiles, nblk,
-                       counts.as<int>());
-    RIOP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(scan_blocks, dim3(nsums), dim3(kScanBlock), 0, st, counts.as<int>(), offsets.as<int>(),
-                       ncounts, sums.as<int>());
-    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums.as<int>(), nsums);
-    hipLaunchKernelGGL(scan_add, dim3(nsums), dim3(kScanBlock), 0, st, offsets.as<int>(), ncounts,
+    hipLaunchKernelGGL(scan_blocks, dim3(nsums), dim3(kScanBlock), 0, st, counts.as<int>(), start, nkeys,
                        sums.as<int>());
-    hipLaunchKernelGGL(tile_start_kernel, dim3((ntiles + 1 + 255) / 256), dim3(256), 0, st, offsets.as<int>(),
-                       ntiles, nblk, M, p->tile_start.as<int>());
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums.as<int>(), nsums);
+    hipLaunchKernelGGL(scan_add, dim3(nsums), dim3(kScanBlock), 0, st, start, nkeys, sums.as<int>());
+    hipLaunchKernelGGL(set_int, dim3(1), dim3(1), 0, st, start, nkeys, (int)M);
     RIOP_HIP(hipGetLastError());
     if (M > 0) {
-        hipLaunchKernelGGL(scatter_kernel<R>, dim3(nblk), dim3(64), lds_tiles, st, tile_of.as<int>(),
-                           cell_of.as<uint32_t>(), frac_of.as<R>(), M, ntiles, nblk, offsets.as<int>(),
-                           p->perm.as<int>(), p->cell.as<uint32_t>(), p->frac.as<R>());
+        RIOP_HIP(hipMemsetAsync(counts.ptr, 0, sizeof(int) * nkeys, st));  // reused as cursors
+        hipLaunchKernelGGL(scatter_by_key, dim3(gM), dim3(threads), 0, st, key_of.as<int>(), M, (const int *)start,
+                           counts.as<int>(), p->perm.as<int>());
+        hipLaunchKernelGGL(key_sort, dim3((unsigned)((nkeys + threads - 1) / threads)), dim3(threads), 0, st,
+                           (const int *)start, nkeys, p->perm.as<int>());
+        hipLaunchKernelGGL(gather_layout<R>, dim3(gM), dim3(threads), 0, st, (const int *)p->perm.as<int>(),
+                           cell_of.as<uint32_t>(), frac_of.as<R>(), M, p->cell.as<uint32_t>(), p->frac.as<R>());
         RIOP_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(tile_start_from_keys, dim3((ntiles + 1 + 255) / 256), dim3(256), 0, st, (const int *)start,
+                       ntiles, T * T, p->tile_start.as<int>());
+    RIOP_HIP(hipGetLastError());
     int hflag = 0;
     std::vector<int> ts(ntiles + 1);
+    std::vector<int> cs((size_t)nkeys + 1);
     RIOP_HIP(hipMemcpyAsync(&hflag, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
     RIOP_HIP(hipMemcpyAsync(ts.data(), p->tile_start.ptr, sizeof(int) * (ntiles + 1), hipMemcpyDeviceToHost, st));
+    RIOP_HIP(hipMemcpyAsync(cs.data(), start, sizeof(int) * (nkeys + 1), hipMemcpyDeviceToHost, st));
     RIOP_HIP(hipStreamSynchronize(st));
     RIOP_REQUIRE(hflag == 0, RIOP_EINVAL, "uv coordinates must be finite and inside [-pi, pi]");
 
-    // Work units: chunks of at most kUnit visibilities of one tile.
-    const int unit = kUnit;
+    // Degridding work units: chunks of at most kUnit visibilities of one tile.
     std::vector<WorkUnit> units;
     int maxc = 0;
     for (int t = 0; t < ntiles; ++t) {
-        const int s = ts[t], e = ts[t + 1];
-        for (int c = s; c < e; c += unit) {
-            const int cnt = std::min(unit, e - c);
+        const int s0 = ts[t], e0 = ts[t + 1];
+        for (int c = s0; c < e0; c += kUnit) {
+            const int cnt = std::min(kUnit, e0 - c);
             units.push_back(WorkUnit{t, c, cnt, 0});
             maxc = std::max(maxc, cnt);
         }
@@ -503,6 +551,31 @@ template <typename R> static void build_layout_t(riop_plan *p, const void *uv, h
     if (!units.empty())
         RIOP_HIP(hipMemcpyAsync(p->units.ptr, units.data(), sizeof(WorkUnit) * units.size(),
                                 hipMemcpyHostToDevice, st));
+
+    // Gridding owner tiles, heaviest first: the work of an owner tile is the
+    // number of visibilities whose first window cell lies in its extended region.
+    const int O = p->owner, ops = K / O, nowner = ops * ops, NR = O + J - 1;
+    std::vector<std::pair<int64_t, int>> work(nowner);
+    for (int ot = 0; ot < nowner; ++ot) {
+        const int oa = (ot / ops) * O, ob = (ot % ops) * O;
+        const int cs0 = (ob - (J - 1) + K) % K, tc0 = cs0 / T, lc0 = cs0 % T;
+        const int len0 = std::min(NR, T - lc0), len1 = NR - len0, tc1 = (tc0 + 1) % tps;
+        int64_t w = 0;
+        for (int r = 0; r < NR; ++r) {
+            const int ar = (oa - (J - 1) + r + K) % K, tr = ar / T, lr = ar % T;
+            const int64_t k0 = (int64_t)(tr * tps + tc0) * T * T + lr * T + lc0;
+            const int64_t k1 = (int64_t)(tr * tps + tc1) * T * T + lr * T;
+            w += cs[k0 + len0] - cs[k0];
+            w += cs[k1 + len1] - cs[k1];
+        }
+        work[ot] = {w, ot};
+    }
+    std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<int> order(nowner);
+    for (int t = 0; t < nowner; ++t) order[t] = work[t].second;
+    p->nowner = nowner;
+    p->owner_order.alloc(sizeof(int) * nowner);
+    RIOP_HIP(hipMemcpyAsync(p->owner_order.ptr, order.data(), sizeof(int) * nowner, hipMemcpyHostToDevice, st));
     RIOP_HIP(hipStreamSynchronize(st));
 }
 
@@ -533,9 +606,11 @@ template <typename R> static GridArgs<R> grid_args(riop_plan *p) {
 
 #define RIOP_J_CASES(MACRO) MACRO(2) MACRO(4) MACRO(6) MACRO(8) MACRO(10) MACRO(12) MACRO(14) MACRO(16)
 
-template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st) {
+template <typename R>
+static void launch_degrid_from(riop_plan *p, const void *grid, void *y, int order_user, hipStream_t st) {
     if (p->nunits == 0) return;
     GridArgs<R> a = grid_args<R>(p);
+    a.grid = const_cast<C<R> *>(static_cast<const C<R> *>(grid));
     a.vout = static_cast<C<R> *>(y);
     a.order_user = order_user;
     const int W = p->tile + p->J - 1;
@@ -556,25 +631,45 @@ template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, 
     RIOP_HIP(hipGetLastError());
 }
 
-template <typename R> void launch_grid(riop_plan *p, const void *y, int order_user, hipStream_t st) {
-    {
-        TimedScope tz(p, KK_GRID_ZERO, st);
-        launch_fill_zero<R>(p->grid.ptr, (size_t)p->K * p->K, st);
-    }
-    if (p->nunits == 0) return;
-    GridArgs<R> a = grid_args<R>(p);
-    a.vin = static_cast<const C<R> *>(y);
-    a.order_user = order_user;
-    const int W = p->tile + p->J - 1;
-    const size_t lds = sizeof(R) * 2 * W * W;
+template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st) {
+    launch_degrid_from<R>(p, p->grid.ptr, y, order_user, st);
+}
+
+template <typename R> static size_t owner_lds(int O, int J, int S) {
+    const int NS = 2 * (O + J - 1);
+    const size_t ints = (size_t)S + 2 * NS + 1;
+    return sizeof(C<R>) * ((size_t)kOwnWaves * O * O + (size_t)S * J) + sizeof(R) * (size_t)S * J +
+           sizeof(int) * (ints + (ints & 1)) + sizeof(R) * (size_t)J * (KDeg<R>::D / 2 + 1);
+}
+
+template <typename R>
+static void launch_owner(riop_plan *p, const void *vals, int order_user, void *out_grid, hipStream_t st) {
+    OwnerArgs<R> a{};
+    a.grid = static_cast<C<R> *>(out_grid);
+    a.cell = p->cell.as<uint32_t>();
+    a.frac = p->frac.as<R>();
+    a.perm = p->perm.as<int>();
+    a.cell_start = p->cell_start.as<int>();
+    a.order = p->owner_order.as<int>();
+    a.vin = static_cast<const C<R> *>(vals);
+    a.kc = p->kcoef_owner.as<R>();
+    a.K = p->K;
+    a.T = p->tile;
+    a.tps = p->tiles_per_side;
+    a.O = p->owner;
+    a.ops = p->K / p->owner;
+    // Staging depth: keeps the kernel within 64 KB of LDS for every width.
+    a.stage = (sizeof(R) == 8 ? 128 : 256) / (p->J > 8 ? 2 : 1);
+    const size_t lds = owner_lds<R>(a.O, p->J, a.stage);
+    RIOP_REQUIRE(lds <= 65536, RIOP_ENOTSUP, "gridding tile too large for LDS");
     TimedScope ts(p, KK_GRID, st);
     switch (p->J) {
-#define GK(JJ) \
-    case JJ:                                                                                          \
-        if (order_user)                                                                               \
-            hipLaunchKernelGGL((grid_kernel<R, JJ, true>), dim3(p->nunits), dim3(kDegridThreads), lds, st, a); \
-        else                                                                                          \
-            hipLaunchKernelGGL((grid_kernel<R, JJ, false>), dim3(p->nunits), dim3(kDegridThreads), lds, st, a); \
+#define GK(JJ)                                                                                                    \
+    case JJ:                                                                                                      \
+        if (order_user)                                                                                           \
+            hipLaunchKernelGGL((grid_owner<R, JJ, true>), dim3(p->nowner), dim3(kOwnThreads), lds, st, a);       \
+        else                                                                                                      \
+            hipLaunchKernelGGL((grid_owner<R, JJ, false>), dim3(p->nowner), dim3(kOwnThreads), lds, st, a);      \
         break;
         RIOP_J_CASES(GK)
 #undef GK
@@ -583,26 +678,14 @@ template <typename R> void launch_grid(riop_plan *p, const void *y, int order_us
     RIOP_HIP(hipGetLastError());
 }
 
+template <typename R> void launch_grid(riop_plan *p, const void *y, int order_user, hipStream_t st) {
+    launch_owner<R>(p, y, order_user, p->grid.ptr, st);
+}
+
+// out_grid = G^T G in_grid: degridding into plan-order scratch, then owner gridding.
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st) {
-    {
-        TimedScope tz(p, KK_GRID_ZERO, st);
-        launch_fill_zero<R>(out_grid, (size_t)p->K * p->K, st);
-    }
-    if (p->nunits == 0) return;
-    GridArgs<R> a = grid_args<R>(p);
-    a.grid = static_cast<C<R> *>(out_grid);
-    const int W = p->tile + p->J - 1;
-    const size_t lds = (sizeof(C<R>) + 2 * sizeof(R)) * W * W;
-    const C<R> *gin = static_cast<const C<R> *>(in_grid);
-    TimedScope ts(p, KK_GRAM, st);
-    switch (p->J) {
-#define GR(JJ) \
-    case JJ: hipLaunchKernelGGL((gram_kernel<R, JJ>), dim3(p->nunits), dim3(kDegridThreads), lds, st, a, gin); break;
-        RIOP_J_CASES(GR)
-#undef GR
-        default: throw Error{RIOP_ENOTSUP, "unsupported kernel width"};
-    }
-    RIOP_HIP(hipGetLastError());
+    launch_degrid_from<R>(p, in_grid, p->vis.ptr, 0, st);
+    launch_owner<R>(p, p->vis.ptr, 0, out_grid, st);
 }
 
 template void launch_gram<float>(riop_plan *, const void *, void *, hipStream_t);

@@ -86,7 +86,8 @@ def test_sorted_variants_follow_layout(prec):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("tile", [8, 32])
 def test_layout_is_stable_counting_sort(prec, tile):
-    """Plan binning is integer work: bit-exact against the window rule and a stable sort."""
+    """Plan binning is integer work: bit-exact against the window rule and a stable sort
+    by (tile, cell inside the tile in row-major order, caller index)."""
     n, M, J = 64, 7777, 8
     device()
     announce(f"layout tile={tile} {prec}")
@@ -98,7 +99,8 @@ def test_layout_is_stable_counting_sort(prec, tile):
     a0 = np.mod(kb.window(g, J), K)                     # (M, 2)
     tiles_per_side = K // tile
     tid = (a0[:, 0] // tile) * tiles_per_side + a0[:, 1] // tile
-    order = np.argsort(tid, kind="stable")
+    key = tid * tile * tile + (a0[:, 0] % tile) * tile + a0[:, 1] % tile
+    order = np.argsort(key, kind="stable")
     np.testing.assert_array_equal(perm, order)
     np.testing.assert_array_equal(cell & 0xFFFF, a0[order, 0])
     np.testing.assert_array_equal(cell >> 16, a0[order, 1])

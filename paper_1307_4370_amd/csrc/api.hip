@@ -348,7 +348,7 @@ static void validate(const riop_desc *d) {
     RIOP_REQUIRE(d->n % (1 << d->levels) == 0, RIOP_ESHAPE, "n must be divisible by 2^levels");
     RIOP_REQUIRE(d->dict_mask != 0 && d->dict_mask < (1u << 9), RIOP_EINVAL, "dict_mask must be in [1, 2^9)");
     RIOP_REQUIRE(d->prec == RIOP_F32 || d->prec == RIOP_F64, RIOP_EINVAL, "prec must be RIOP_F32 or RIOP_F64");
-    for (int i = 0; i < 7; ++i) RIOP_REQUIRE(d->reserved[i] == 0, RIOP_EINVAL, "reserved fields must be zero");
+    for (int i = 0; i < 6; ++i) RIOP_REQUIRE(d->reserved[i] == 0, RIOP_EINVAL, "reserved fields must be zero");
     if (d->tile) {
         const int t = d->tile;
         RIOP_REQUIRE(t >= 8 && t <= 64 && (t & (t - 1)) == 0 && (2 * d->n) % t == 0, RIOP_EINVAL,
@@ -419,7 +419,12 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         p->tile = desc->tile ? desc->tile : default_tile(p->K, p->J);
         RIOP_REQUIRE(p->tile >= p->J && p->K % p->tile == 0, RIOP_EINVAL,
                      "gridding tile must be at least J and divide 2n");
-        p->owner = std::min(p->tile, p->prec == RIOP_F64 ? 16 : 32);
+        {
+            int v = 0;
+            RIOP_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+            p->lds_max = (size_t)std::max(v, 0);
+        }
+        choose_owner(p, desc->grid_owner);
         p->tiles_per_side = p->K / p->tile;
         p->ntiles = p->tiles_per_side * p->tiles_per_side;
         RIOP_REQUIRE(p->ntiles <= 16384, RIOP_ENOTSUP, "too many gridding tiles; use a larger tile");
@@ -472,6 +477,7 @@ riop_status riop_plan_info(const riop_plan *p, riop_info *info) {
         info->prec = p->prec;
         info->M = p->M;
         info->tile = p->tile;
+        info->grid_owner = p->owner;
         info->ntiles = p->ntiles;
         info->nunits = p->nunits;
         info->kernel_degree = p->kdeg;

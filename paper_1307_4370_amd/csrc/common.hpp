@@ -145,6 +145,7 @@ struct riop_plan {
     // Visibility layout (plan order).
     int tile = 0, tiles_per_side = 0, ntiles = 0;
     int owner = 0, nowner = 0;  // gridding owner tile side (divides tile) and count
+    size_t lds_max = 65536;     // LDS bytes one workgroup may use on the plan's device
     riop::DevBuf perm;        // int32[M]
     riop::DevBuf cell;        // uint32[M]: a0 | b0 << 16
     riop::DevBuf frac;        // R[2M]: (rho_u, rho_v)
@@ -198,6 +199,11 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
 template <typename R>
 void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid = nullptr);
 // out_grid = G^T G in_grid (fused degrid + grid, the Gram part of Phi^dagger Phi).
+// Row stride (complex elements) of a private owner tile in LDS: 8 elements of
+// padding shift consecutive rows by 16 banks (FP32) or 32 banks (FP64).
+inline int owner_stride(int O) { return O + 8; }
+// Picks the gridding owner tile side (0 = library choice).
+void choose_owner(riop_plan *p, int want_owner);
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
 template <typename R>
 void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st);

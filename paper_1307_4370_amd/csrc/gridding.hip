@@ -210,9 +210,10 @@ __device__ inline void kb_weights(R rho, const KCoef<R> &kc, R (&w)[J]) {
     }
 }
 
-// Same weights with the coefficient table in LDS, laid out [pair][even/odd][KS].
+// Same weights with the coefficient table read through a pointer (global,
+// wave-uniform: scalar loads), laid out [pair][even/odd][KS].
 template <typename R, int J>
-__device__ inline void kb_weights_lds(R rho, const R *kc, R (&w)[J]) {
+__device__ inline void kb_weights_ptr(R rho, const R *__restrict__ kc, R (&w)[J]) {
     constexpr int D = KDeg<R>::D;
     constexpr int NEV = D / 2 + 1, NOD = (D + 1) / 2, KS = D / 2 + 1;
     const R s = R(2) * rho - R(1);
@@ -320,39 +321,66 @@ template <typename R> struct OwnerArgs {
     const int *cell_start;    // K^2 + 1 plan-order offsets of the cell keys
     const int *order;         // owner tiles, heaviest first
     const C<R> *vin;          // values to grid
-    const R *kc;              // kernel coefficients [pair][even/odd][D/2 + 1]
+    const R *__restrict__ kc; // kernel coefficients [pair][even/odd][D/2 + 1]
     int K, T, tps;            // grid side, sort tile side, sort tiles per side
-    int O, ops;               // owner tile side (divides T), owner tiles per side
-    int stage;                // visibilities staged per chunk
+    int O, OS, ops;           // owner tile side (divides T), LDS row stride, owner tiles per side
 };
 
-// Lane (i, j) of a wavefront covers window cells (i + 8p, j + 8q), p, q < NB.
+// Padded row length of a wavefront's tap-major staging arrays: consecutive
+// taps start 8 (complex) or 4 (real) banks apart, so the stores of the
+// staging step (consecutive lanes, consecutive entries) and the eight-address
+// broadcast reads of the accumulation step are free of bank conflicts.
+template <typename R> __host__ __device__ constexpr int slice_row() { return 64 + (sizeof(R) == 4 ? 4 : 2); }
+
+template <typename R> static size_t owner_lds(int O, int OS, int J) {
+    const int NS = 2 * (O + J - 1);
+    return sizeof(C<R>) * (size_t)kOwnWaves * (O * OS + 64) + (sizeof(C<R>) + sizeof(R)) * (size_t)kOwnWaves * J * slice_row<R>() +
+           sizeof(R) * (size_t)J * (KDeg<R>::D / 2 + 1) + sizeof(int) * (2 * (size_t)NS + 1);
+}
+
+// One workgroup per O x O owner tile; its wavefronts split the visibilities
+// whose windows reach the tile (contiguous in plan order per segment) into
+// contiguous shares and work independently, 64 visibilities (a slice) at a
+// time.  Staging: lane t of the wavefront takes visibility t of the slice and
+// writes its J row weights times the value and its J column weights to the
+// wavefront's own LDS area.  Accumulation: the wavefront walks the slice one
+// visibility per step, lane (i, j) holding window cells (i + 8p, j + 8q).
+// Equal cells are consecutive in plan order, so a run is summed in registers
+// and added to the wavefront's private copy of the tile only where the cell
+// changes (a bit mask built by one ballot per slice).  No workgroup barrier
+// inside the loop: a wavefront reads only what it staged itself.
 template <typename R, int J, bool USER>
 __global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
     constexpr int NB = (J + 7) / 8;
-    extern __shared__ unsigned char smem_raw[];
-    const int T = a.T, K = a.K, tps = a.tps, S = a.stage, O = a.O, O2 = O * O;
-    const int NR = O + J - 1, NS = 2 * NR;
-    // LDS layout.
-    C<R> *priv = reinterpret_cast<C<R> *>(smem_raw);             // [waves][O*O]
-    C<R> *wuv = priv + kOwnWaves * O2;                           // [S][J]: wu_i * value
-    R *wvs = reinterpret_cast<R *>(wuv + (size_t)S * J);         // [S][J]
-    int *spos = reinterpret_cast<int *>(wvs + (size_t)S * J);    // [S]: (la + J) << 8 | (lb + J)
-    int *segbeg = spos + S;                                      // [NS]
-    int *segoff = segbeg + NS;                                   // [NS + 1]
+    constexpr int BATCH = sizeof(R) == 8 ? (J > 12 ? 2 : 4) : (J > 8 ? 4 : 8);
+    constexpr int SR = slice_row<R>();
+    // Kernel coefficients through scalar loads where they fit in scalar
+    // registers alongside everything else, else from an LDS copy.
+    constexpr bool kScalarCoef = sizeof(R) == 4 && J <= 12;
+    constexpr bool kUnroll = !(sizeof(R) == 8 && J > 12);
     constexpr int KS = KDeg<R>::D / 2 + 1;
-    R *kcl = reinterpret_cast<R *>(segoff + NS + 1 + ((NS + 1) & 1));  // [J/2][2][KS], 8-byte aligned
-    for (int i = threadIdx.x; i < (J / 2) * 2 * KS; i += blockDim.x) kcl[i] = a.kc[i];
+    extern __shared__ unsigned char smem_raw[];
+    const int T = a.T, K = a.K, tps = a.tps, O = a.O, OS = a.OS, PS = O * OS + 64;
+    const int NR = O + J - 1, NS = 2 * NR;
+    C<R> *priv = reinterpret_cast<C<R> *>(smem_raw);                     // [waves][O * OS + 64 trash cells]
+    C<R> *wuv_all = priv + kOwnWaves * PS;                               // [waves][J][SR]: wu_i * value
+    R *wv_all = reinterpret_cast<R *>(wuv_all + (size_t)kOwnWaves * J * SR);  // [waves][J][SR]
+    R *kcl = wv_all + (size_t)kOwnWaves * J * SR;                        // [J/2][2][KS]
+    int *segbeg = reinterpret_cast<int *>(kcl + (J / 2) * 2 * KS);        // [NS]
+    int *segoff = segbeg + NS;                                           // [NS + 1]
+    const int tid = threadIdx.x;
+    if constexpr (!kScalarCoef)
+        for (int i = tid; i < (J / 2) * 2 * KS; i += kOwnThreads) kcl[i] = a.kc[i];
 
     const int ot = a.order[blockIdx.x];
     const int oa = (ot / a.ops) * O, ob = (ot % a.ops) * O;
     // Extended region: base-cell rows oa - (J-1) .. oa + O - 1 and columns
     // ob - (J-1) .. ob + O - 1 (mod K).  Each row is split at the sort-tile
-    // boundary into at most two key-contiguous pieces.
+    // boundary into at most two key-contiguous pieces (O divides T, J <= T).
     const int cs = (ob - (J - 1) + K) % K;
     const int tc0 = cs / T, lc0 = cs % T;
     const int len0 = min(NR, T - lc0), len1 = NR - len0, tc1 = (tc0 + 1) % tps;
-    for (int sgi = threadIdx.x; sgi < NS; sgi += blockDim.x) {
+    for (int sgi = tid; sgi < NS; sgi += kOwnThreads) {
         const int r = sgi >> 1, piece = sgi & 1;
         const int ar = (oa - (J - 1) + r + K) % K;
         const int tr = ar / T, lr = ar % T;
@@ -361,100 +389,198 @@ __global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
         segbeg[sgi] = b;
         segoff[sgi + 1] = a.cell_start[k0 + (piece ? len1 : len0)] - b;
     }
-    for (int c = threadIdx.x; c < kOwnWaves * O2; c += blockDim.x) priv[c] = mk<R>(0, 0);
+    for (int c = tid; c < kOwnWaves * PS; c += kOwnThreads) priv[c] = mk<R>(0, 0);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         segoff[0] = 0;
         for (int k = 0; k < NS; ++k) segoff[k + 1] += segoff[k];
     }
     __syncthreads();
     const int total = segoff[NS];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane >> 3, lj = lane & 7;
-    C<R> *mine = priv + wave * O2;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, li = lane >> 3, lj = lane & 7;
+    C<R> *mine = priv + wave * PS;
+    C<R> *wuv = wuv_all + wave * J * SR;
+    R *wv = wv_all + wave * J * SR;
 
-    for (int chunk = 0; chunk < total; chunk += S) {
-        const int cnt = min(S, total - chunk);
-        // Phase 1: one visibility per thread -> weights and value into LDS.
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int f = chunk + t;
-            int lo = 0, hi = NS;  // segoff[lo] <= f < segoff[hi]
+    // This wavefront's slices.
+    const int nsl = (total + 63) >> 6;
+    const int s_begin = (wave * nsl) / kOwnWaves, s_end = ((wave + 1) * nsl) / kOwnWaves;
+
+    // Visibility staged next by this lane: segment, cell, offsets, value.
+    // A lane's position advances by 64 per slice, so the segment search
+    // runs only when some lane has left its segment.
+    int seg = 0;
+    uint32_t cv = 0;
+    R fu = 0, fv = 0;
+    C<R> val = mk<R>(0, 0);
+    auto fetch = [&](int f) {
+        const bool in = f < total;
+        const bool moved = in && segoff[seg + 1] <= f;
+        if (__ballot(moved)) {
+            if (moved) {
+                int lo = seg + 1, hi = NS;  // segoff[lo] <= f < segoff[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (segoff[mid] <= f) lo = mid; else hi = mid;
+                }
+                seg = lo;
+            }
+        }
+        if (in) {
+            const int v = segbeg[seg] + (f - segoff[seg]);
+            cv = a.cell[v];
+            fu = a.frac[2 * (int64_t)v];
+            fv = a.frac[2 * (int64_t)v + 1];
+            val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
+        }
+    };
+    if (s_begin < s_end) {
+        // First slice: full search from the first segment.
+        const int f = s_begin * 64 + lane;
+        if (f < total) {
+            int lo = 0, hi = NS;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (segoff[mid] <= f) lo = mid; else hi = mid;
             }
-            const int v = segbeg[lo] + (f - segoff[lo]);
-            const int r = lo >> 1, piece = lo & 1;
-            const uint32_t cv = a.cell[v];
-            const int la = r - (J - 1);
-            const int lb = (int)(cv >> 16) % T + (piece ? len0 : -lc0) - (J - 1);
+            seg = lo;
+        }
+        fetch(f);
+    }
+
+    int ic[NB], jc[NB];
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+        ic[p] = min(li + 8 * p, J - 1) * SR;
+        jc[p] = min(lj + 8 * p, J - 1) * SR;
+    }
+    // The open run: its cells' addresses in the private copy (lanes whose
+    // cell lies outside the owner tile use a trash cell of their own), the
+    // values read from there when the run opened, and the sum of its
+    // contributions so far.  Closing the run adds and stores; the read was
+    // issued when the run opened, so its latency hides behind the run.
+    C<R> acc[NB][NB], g[NB][NB];
+    int addr[NB][NB];
+#pragma unroll
+    for (int p = 0; p < NB; ++p)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            acc[p][q] = mk<R>(0, 0);
+            g[p][q] = mk<R>(0, 0);
+            addr[p][q] = O * OS + lane;
+        }
+    auto close_run = [&]() {
+#pragma unroll
+        for (int p = 0; p < NB; ++p)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                g[p][q].x += acc[p][q].x;
+                g[p][q].y += acc[p][q].y;
+                mine[addr[p][q]] = g[p][q];
+                acc[p][q] = mk<R>(0, 0);
+            }
+    };
+    auto open_run = [&](int pos) {
+        const int la = (pos >> 8) - J, lb = (pos & 255) - J;
+#pragma unroll
+        for (int p = 0; p < NB; ++p)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int i = li + 8 * p, j = lj + 8 * q;
+                const int ra = la + i, rb = lb + j;
+                const bool ok = i < J && j < J && (unsigned)ra < (unsigned)O && (unsigned)rb < (unsigned)O;
+                addr[p][q] = ok ? ra * OS + rb : O * OS + lane;
+            }
+#pragma unroll
+        for (int p = 0; p < NB; ++p)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) g[p][q] = mine[addr[p][q]];
+    };
+    int cur = -1;  // packed cell of the open run (-1: none yet)
+
+    for (int sl = s_begin; sl < s_end; ++sl) {
+        const int base = sl * 64;
+        const bool live = base + lane < total;
+        // Staging.  Lanes past the end stage zero values, so the
+        // accumulation below runs over all 64 entries without bound tests.
+        if (!live) val = mk<R>(0, 0);
+        const int r = seg >> 1, piece = seg & 1;
+        const int la = r - (J - 1);
+        const int lb = (int)(cv >> 16) % T + (piece ? len0 : -lc0) - (J - 1);
+        const int pos = live ? ((la + J) << 8) | (lb + J) : -1;
+        {
             R wu_[J], wv_[J];
-            kb_weights_lds<R, J>(a.frac[2 * (int64_t)v], kcl, wu_);
-            kb_weights_lds<R, J>(a.frac[2 * (int64_t)v + 1], kcl, wv_);
-            const C<R> val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
+            if constexpr (kScalarCoef) {
+                kb_weights_ptr<R, J>(fu, a.kc, wu_);
+                kb_weights_ptr<R, J>(fv, a.kc, wv_);
+            } else {
+                kb_weights_ptr<R, J>(fu, kcl, wu_);
+                kb_weights_ptr<R, J>(fv, kcl, wv_);
+            }
 #pragma unroll
             for (int i = 0; i < J; ++i) {
-                wuv[t * J + i] = mk<R>(wu_[i] * val.x, wu_[i] * val.y);
-                wvs[t * J + i] = wv_[i];
+                wuv[i * SR + lane] = mk<R>(wu_[i] * val.x, wu_[i] * val.y);
+                wv[i * SR + lane] = wv_[i];
             }
-            spos[t] = ((la + J) << 8) | (lb + J);
         }
-        __syncthreads();
-        // Phase 2: one staged visibility per step for each wavefront; runs of
-        // equal cells are summed in registers and added to the wave's copy.
-        const int per = (cnt + kOwnWaves - 1) / kOwnWaves;
-        const int e0 = wave * per, e1 = min(cnt, e0 + per);
-        if (e0 < e1) {
-            C<R> acc[NB][NB];
+        // Run starts: entries whose cell differs from the previous entry's.
+        int prev = __shfl_up(pos, 1);
+        if (lane == 0) prev = cur;
+        const uint64_t starts = __ballot(live && pos != prev);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (sl + 1 < s_end) fetch(base + 64 + lane);  // global loads in flight during the accumulation
+
+        // Accumulation: one staged visibility per step; unrolled over the
+        // slice (constant bit tests, immediate offsets) where registers allow.
+        auto batch = [&](int kb) {
+            C<R> us[BATCH][NB];
+            R ws[BATCH][NB];
 #pragma unroll
-            for (int p = 0; p < NB; ++p)
+            for (int k = 0; k < BATCH; ++k)
 #pragma unroll
-                for (int q = 0; q < NB; ++q) acc[p][q] = mk<R>(0, 0);
-            int cur = spos[e0];
-            auto flush = [&](int pos) {
-                const int la = (pos >> 8) - J, lb = (pos & 255) - J;
+                for (int p = 0; p < NB; ++p) {
+                    us[k][p] = wuv[ic[p] + kb + k];
+                    ws[k][p] = wv[jc[p] + kb + k];
+                }
 #pragma unroll
-                for (int p = 0; p < NB; ++p)
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) {
-                        const int i = li + 8 * p, j = lj + 8 * q;
-                        const int ra = la + i, rb = lb + j;
-                        if (i < J && j < J && ra >= 0 && ra < O && rb >= 0 && rb < O) {
-                            C<R> g = mine[ra * O + rb];
-                            g.x += acc[p][q].x;
-                            g.y += acc[p][q].y;
-                            mine[ra * O + rb] = g;
-                        }
-                        acc[p][q] = mk<R>(0, 0);
-                    }
-            };
-            for (int e = e0; e < e1; ++e) {
-                const int pos = spos[e];
-                if (pos != cur) {
-                    flush(cur);
-                    cur = pos;
+            for (int k = 0; k < BATCH; ++k) {
+                if (__builtin_expect((starts >> (kb + k)) & 1, 0)) {
+                    if (cur >= 0) close_run();
+                    cur = __builtin_amdgcn_readlane(pos, kb + k);
+                    open_run(cur);
                 }
 #pragma unroll
                 for (int p = 0; p < NB; ++p)
 #pragma unroll
                     for (int q = 0; q < NB; ++q) {
-                        const int i = li + 8 * p, j = lj + 8 * q;
-                        if (i < J && j < J) {
-                            const C<R> u = wuv[e * J + i];
-                            const R w = wvs[e * J + j];
-                            acc[p][q].x += u.x * w;
-                            acc[p][q].y += u.y * w;
-                        }
+                        acc[p][q].x += us[k][p].x * ws[k][q];
+                        acc[p][q].y += us[k][p].y * ws[k][q];
                     }
             }
-            flush(cur);
+        };
+        if constexpr (kUnroll) {
+#pragma unroll
+            for (int kb = 0; kb < 64; kb += BATCH) batch(kb);
+        } else {
+#pragma unroll 1
+            for (int kb = 0; kb < 64; kb += BATCH) batch(kb);
         }
-        __syncthreads();
+        // The next slice's staging overwrites this one.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    if (cur >= 0) close_run();
+    __syncthreads();
     // Sum the private copies in wave order and store the tile.
-    for (int c = threadIdx.x; c < O2; c += blockDim.x) {
-        C<R> sum = priv[c];
-        for (int w = 1; w < kOwnWaves; ++w) sum = cadd<R>(sum, priv[w * O2 + c]);
-        a.grid[(int64_t)(oa + c / O) * K + ob + c % O] = sum;
+    for (int c = tid; c < O * O; c += kOwnThreads) {
+        const int r = c / O, col = c - r * O;
+        C<R> sum = priv[r * OS + col];
+        for (int w = 1; w < kOwnWaves; ++w) sum = cadd<R>(sum, priv[w * PS + r * OS + col]);
+        a.grid[(int64_t)(oa + r) * K + ob + col] = sum;
     }
 }
 
@@ -635,11 +761,14 @@ template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, 
     launch_degrid_from<R>(p, p->grid.ptr, y, order_user, st);
 }
 
-template <typename R> static size_t owner_lds(int O, int J, int S) {
-    const int NS = 2 * (O + J - 1);
-    const size_t ints = (size_t)S + 2 * NS + 1;
-    return sizeof(C<R>) * ((size_t)kOwnWaves * O * O + (size_t)S * J) + sizeof(R) * (size_t)S * J +
-           sizeof(int) * (ints + (ints & 1)) + sizeof(R) * (size_t)J * (KDeg<R>::D / 2 + 1);
+void choose_owner(riop_plan *p, int want_owner) {
+    const bool f64 = p->prec == RIOP_F64;
+    const int O = want_owner ? want_owner : std::min(p->tile, f64 ? 16 : 32);
+    RIOP_REQUIRE(O >= 8 && O <= p->tile && (O & (O - 1)) == 0, RIOP_EINVAL,
+                 "grid_owner must be a power of two in [8, tile]");
+    const size_t lds = f64 ? owner_lds<double>(O, owner_stride(O), p->J) : owner_lds<float>(O, owner_stride(O), p->J);
+    RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding owner tile too large for LDS");
+    p->owner = O;
 }
 
 template <typename R>
@@ -657,11 +786,10 @@ static void launch_owner(riop_plan *p, const void *vals, int order_user, void *o
     a.T = p->tile;
     a.tps = p->tiles_per_side;
     a.O = p->owner;
+    a.OS = owner_stride(p->owner);
     a.ops = p->K / p->owner;
-    // Staging depth: keeps the kernel within 64 KB of LDS for every width.
-    a.stage = (sizeof(R) == 8 ? 128 : 256) / (p->J > 8 ? 2 : 1);
-    const size_t lds = owner_lds<R>(a.O, p->J, a.stage);
-    RIOP_REQUIRE(lds <= 65536, RIOP_ENOTSUP, "gridding tile too large for LDS");
+    const size_t lds = owner_lds<R>(a.O, a.OS, p->J);
+    RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding owner tile too large for LDS");
     TimedScope ts(p, KK_GRID, st);
     switch (p->J) {
 #define GK(JJ)                                                                                                    \

@@ -446,7 +446,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         build_layout(p, uv, s);
         p->device_bytes = 0;
         for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->cell_start,
-                                &p->owner_order, &p->kcoef, &p->kcoef_owner, &p->deapod,
+                                &p->owner_order, &p->owner_count, &p->kcoef, &p->kcoef_owner, &p->deapod,
                                 &p->fft.twiddle, &p->tmp, &p->grid, &p->grid2, &p->vis, &p->img, &p->filters, &p->ll})
             p->device_bytes += (int64_t)b->bytes;
     });

@@ -152,7 +152,8 @@ struct riop_plan {
     riop::DevBuf tile_start;  // int32[ntiles + 1]
     riop::DevBuf units;       // WorkUnit[nunits] (degridding)
     riop::DevBuf cell_start;  // int32[K^2 + 1]: plan-order start of each cell key
-    riop::DevBuf owner_order; // int32[ntiles]: gridding tiles, heaviest first
+    riop::DevBuf owner_order; // int32[nowner]: gridding owner tiles, heaviest first
+    riop::DevBuf owner_count; // int32[nowner]: visibilities whose windows reach each owner tile
     int nunits = 0;
     int max_unit = 0;
 
@@ -199,9 +200,9 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
 template <typename R>
 void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid = nullptr);
 // out_grid = G^T G in_grid (fused degrid + grid, the Gram part of Phi^dagger Phi).
-// Row stride (complex elements) of a private owner tile in LDS: 8 elements of
-// padding shift consecutive rows by 16 banks (FP32) or 32 banks (FP64).
-inline int owner_stride(int O) { return O + 8; }
+// Row stride (doubles) of the owner tile planes in LDS: 4 elements of padding
+// shift consecutive rows by 8 banks.
+inline int owner_stride(int O) { return O + 4; }
 // Picks the gridding owner tile side (0 = library choice).
 void choose_owner(riop_plan *p, int want_owner);
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);

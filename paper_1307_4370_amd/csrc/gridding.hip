@@ -310,8 +310,6 @@ __global__ void __launch_bounds__(kDegridThreads) degrid_kernel(GridArgs<R> a) {
 // ---------------------------------------------------------------------------
 // Gridding, owner computes.
 
-constexpr int kOwnThreads = 256;  // 4 wavefronts
-constexpr int kOwnWaves = kOwnThreads / 64;
 
 template <typename R> struct OwnerArgs {
     C<R> *grid;               // output grid: every owned cell is written
@@ -320,60 +318,102 @@ template <typename R> struct OwnerArgs {
     const int *perm;          // plan order -> caller order
     const int *cell_start;    // K^2 + 1 plan-order offsets of the cell keys
     const int *order;         // owner tiles, heaviest first
+    const int *count;         // visibilities whose windows reach each owner tile
     const C<R> *vin;          // values to grid
     const R *__restrict__ kc; // kernel coefficients [pair][even/odd][D/2 + 1]
     int K, T, tps;            // grid side, sort tile side, sort tiles per side
     int O, OS, ops;           // owner tile side (divides T), LDS row stride, owner tiles per side
 };
 
-// Padded row length of a wavefront's tap-major staging arrays: consecutive
-// taps start 8 (complex) or 4 (real) banks apart, so the stores of the
-// staging step (consecutive lanes, consecutive entries) and the eight-address
-// broadcast reads of the accumulation step are free of bank conflicts.
-template <typename R> __host__ __device__ constexpr int slice_row() { return 64 + (sizeof(R) == 4 ? 4 : 2); }
+// Single-precision windows up to 8 wide are accumulated with matrix
+// instructions (v_mfma_f32_16x16x4_f32), the others with vector FMAs.
+template <typename R> __host__ __device__ constexpr bool owner_mfma(int J) { return sizeof(R) == 4 && J <= 8; }
 
-template <typename R> static size_t owner_lds(int O, int OS, int J) {
+// Row length of a wavefront's tap-major staging arrays.  Vector path: odd,
+// so the eight-address broadcast reads fall in distinct banks.  Matrix path:
+// 4 mod 32, so the operand reads (16 rows x 4 entries per instruction) hit 64
+// distinct banks.  Either way the staging stores (consecutive lanes) are
+// conflict-free.
+template <typename R> __host__ __device__ constexpr int slice_row(int J) { return owner_mfma<R>(J) ? 68 : 65; }
+
+// LDS bytes of one wavefront's staging area.
+template <typename R> __host__ __device__ constexpr int owner_stage_bytes(int J) {
+    return ((int)sizeof(C<R>) * (owner_mfma<R>(J) ? 8 : J) + (int)sizeof(R) * 8 * ((J + 7) / 8 + 1)) * slice_row<R>(J);
+}
+
+// Wavefronts per owner workgroup: of 6, 4 and 2, the count that keeps the
+// most wavefronts resident per CU (160 KB of LDS, 32 x 32 owner tile),
+// preferring more wavefronts per tile on ties (shorter heavy tiles).
+template <typename R> __host__ __device__ constexpr int owner_waves(int J) {
+    const int tile = 2 * 8 * 32 * 36 + 2048;
+    const int st = owner_stage_bytes<R>(J);
+    const int w6 = 6 * (163840 / (6 * st + tile)), w4 = 4 * (163840 / (4 * st + tile)), w2 = 2 * (163840 / (2 * st + tile));
+    return (w6 >= w4 && w6 >= w2 && w6 > 0) ? 6 : (w4 >= w2 && w4 > 0) ? 4 : 2;
+}
+
+template <typename R> static size_t owner_lds(int O, int OS, int J, int waves) {
     const int NS = 2 * (O + J - 1);
-    return sizeof(C<R>) * (size_t)kOwnWaves * (O * OS + 64) + (sizeof(C<R>) + sizeof(R)) * (size_t)kOwnWaves * J * slice_row<R>() +
+    return sizeof(double) * 2 * (size_t)O * OS + (size_t)owner_stage_bytes<R>(J) * waves +
            sizeof(R) * (size_t)J * (KDeg<R>::D / 2 + 1) + sizeof(int) * (2 * (size_t)NS + 1);
 }
 
 // One workgroup per O x O owner tile; its wavefronts split the visibilities
 // whose windows reach the tile (contiguous in plan order per segment) into
 // contiguous shares and work independently, 64 visibilities (a slice) at a
-// time.  Staging: lane t of the wavefront takes visibility t of the slice and
-// writes its J row weights times the value and its J column weights to the
-// wavefront's own LDS area.  Accumulation: the wavefront walks the slice one
-// visibility per step, lane (i, j) holding window cells (i + 8p, j + 8q).
-// Equal cells are consecutive in plan order, so a run is summed in registers
-// and added to the wavefront's private copy of the tile only where the cell
-// changes (a bit mask built by one ballot per slice).  No workgroup barrier
-// inside the loop: a wavefront reads only what it staged itself.
+// time.
+//
+// Staging: lane t of the wavefront takes visibility t of the slice and writes
+// its J row weights times the value, and its J column weights shifted by the
+// window's column offset inside an 8-aligned column block (zeros around them),
+// to the wavefront's own LDS area.
+//
+// Accumulation: the wavefront walks the slice one visibility per step; lane
+// (i, j) holds rows i + 8p of the window and columns j + 8q of the 8 (NB + 1)
+// wide column range that starts at the block.  In plan order, visibilities of
+// one window row and one column block are consecutive, so such a run is
+// summed in registers and added to the workgroup's tile only where it ends
+// (a bit mask built by one ballot per slice), with LDS double-precision atomic
+// adds: the tile is held in double for both precisions (on this GPU the double
+// LDS atomic is several times faster than the single one).  No workgroup
+// barrier inside the loop: a wavefront reads only what it staged itself.
 template <typename R, int J, bool USER>
-__global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
-    constexpr int NB = (J + 7) / 8;
+__global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R> a) {
+    constexpr int kOwnWaves = owner_waves<R>(J), kOwnThreads = 64 * kOwnWaves;
+    constexpr int NB = (J + 7) / 8;  // row slots per lane
+    constexpr int QB = NB + 1;       // column slots per lane
+    constexpr int NC = 8 * QB;       // staged column-weight rows
+    constexpr bool MF = owner_mfma<R>(J);
+    constexpr int JR = MF ? 8 : J;   // staged row-weight rows
+    constexpr int SR = slice_row<R>(J);
     constexpr int BATCH = sizeof(R) == 8 ? (J > 12 ? 2 : 4) : (J > 8 ? 4 : 8);
-    constexpr int SR = slice_row<R>();
     // Kernel coefficients through scalar loads where they fit in scalar
     // registers alongside everything else, else from an LDS copy.
     constexpr bool kScalarCoef = sizeof(R) == 4 && J <= 12;
     constexpr bool kUnroll = !(sizeof(R) == 8 && J > 12);
     constexpr int KS = KDeg<R>::D / 2 + 1;
     extern __shared__ unsigned char smem_raw[];
-    const int T = a.T, K = a.K, tps = a.tps, O = a.O, OS = a.OS, PS = O * OS + 64;
+    const int T = a.T, K = a.K, tps = a.tps, O = a.O, OS = a.OS, PS = O * OS;
     const int NR = O + J - 1, NS = 2 * NR;
-    C<R> *priv = reinterpret_cast<C<R> *>(smem_raw);                     // [waves][O * OS + 64 trash cells]
-    C<R> *wuv_all = priv + kOwnWaves * PS;                               // [waves][J][SR]: wu_i * value
-    R *wv_all = reinterpret_cast<R *>(wuv_all + (size_t)kOwnWaves * J * SR);  // [waves][J][SR]
-    R *kcl = wv_all + (size_t)kOwnWaves * J * SR;                        // [J/2][2][KS]
-    int *segbeg = reinterpret_cast<int *>(kcl + (J / 2) * 2 * KS);        // [NS]
-    int *segoff = segbeg + NS;                                           // [NS + 1]
+    double *tre = reinterpret_cast<double *>(smem_raw);                   // [O][OS] real parts
+    double *tim = tre + PS;                                               // [O][OS] imaginary parts
+    C<R> *wuv_all = reinterpret_cast<C<R> *>(tim + PS);                   // [waves][JR][SR]: wu_i * value
+    R *wv_all = reinterpret_cast<R *>(wuv_all + (size_t)kOwnWaves * JR * SR);  // [waves][NC][SR]
+    R *kcl = wv_all + (size_t)kOwnWaves * NC * SR;                        // [J/2][2][KS]
+    int *segbeg = reinterpret_cast<int *>(kcl + (J / 2) * 2 * KS);         // [NS]
+    int *segoff = segbeg + NS;                                            // [NS + 1]
     const int tid = threadIdx.x;
     if constexpr (!kScalarCoef)
         for (int i = tid; i < (J / 2) * 2 * KS; i += kOwnThreads) kcl[i] = a.kc[i];
 
     const int ot = a.order[blockIdx.x];
     const int oa = (ot / a.ops) * O, ob = (ot % a.ops) * O;
+    if (a.count[ot] == 0) {  // no window reaches the tile
+        for (int c = tid; c < O * O; c += kOwnThreads) {
+            const int r = c / O, col = c - r * O;
+            a.grid[(int64_t)(oa + r) * K + ob + col] = mk<R>(0, 0);
+        }
+        return;
+    }
     // Extended region: base-cell rows oa - (J-1) .. oa + O - 1 and columns
     // ob - (J-1) .. ob + O - 1 (mod K).  Each row is split at the sort-tile
     // boundary into at most two key-contiguous pieces (O divides T, J <= T).
@@ -389,115 +429,131 @@ __global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
         segbeg[sgi] = b;
         segoff[sgi + 1] = a.cell_start[k0 + (piece ? len1 : len0)] - b;
     }
-    for (int c = tid; c < kOwnWaves * PS; c += kOwnThreads) priv[c] = mk<R>(0, 0);
+    for (int c = tid; c < 2 * PS; c += kOwnThreads) tre[c] = 0.0;
     __syncthreads();
-    if (tid == 0) {
-        segoff[0] = 0;
-        for (int k = 0; k < NS; ++k) segoff[k + 1] += segoff[k];
+    if (tid < 64) {
+        // Scan of the segment lengths by the first wavefront: lane l holds
+        // segments 4l .. 4l + 3 (NS <= 2 * (64 + 15) < 256).
+        int len[4], x = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = 4 * tid + m + 1;
+            len[m] = k <= NS ? segoff[k] : 0;
+            x += len[m];
+        }
+        const int own = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d);
+            if (tid >= d) x += y;
+        }
+        int run = x - own;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = 4 * tid + m + 1;
+            run += len[m];
+            if (k <= NS) segoff[k] = run;
+        }
+        if (tid == 0) segoff[0] = 0;
     }
     __syncthreads();
     const int total = segoff[NS];
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, li = lane >> 3, lj = lane & 7;
-    C<R> *mine = priv + wave * PS;
-    C<R> *wuv = wuv_all + wave * J * SR;
-    R *wv = wv_all + wave * J * SR;
+    C<R> *wuv = wuv_all + wave * JR * SR;
+    R *wv = wv_all + wave * NC * SR;
+    // Matrix path: row-weight rows J .. 7 are never staged and stay zero.
+    if constexpr (MF)
+        for (int i = J * SR + lane; i < JR * SR; i += 64) wuv[i] = mk<R>(0, 0);
 
     // This wavefront's slices.
     const int nsl = (total + 63) >> 6;
     const int s_begin = (wave * nsl) / kOwnWaves, s_end = ((wave + 1) * nsl) / kOwnWaves;
 
-    // Visibility staged next by this lane: segment, cell, offsets, value.
-    // A lane's position advances by 64 per slice, so the segment search
-    // runs only when some lane has left its segment.
-    int seg = 0;
+    // The visibility this lane stages next: its segment, the slice position
+    // where the segment ends, its plan index, cell, offsets and value.  A
+    // lane's position advances by 64 per slice, so the segment search runs
+    // only when the lane leaves its segment.
+    int seg = 0, bnd = 0, v = 0;
     uint32_t cv = 0;
     R fu = 0, fv = 0;
     C<R> val = mk<R>(0, 0);
-    auto fetch = [&](int f) {
-        const bool in = f < total;
-        const bool moved = in && segoff[seg + 1] <= f;
-        if (__ballot(moved)) {
-            if (moved) {
-                int lo = seg + 1, hi = NS;  // segoff[lo] <= f < segoff[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (segoff[mid] <= f) lo = mid; else hi = mid;
-                }
-                seg = lo;
-            }
+    auto locate = [&](int f, int lo) {
+        int hi = NS;  // segoff[lo] <= f < segoff[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segoff[mid] <= f) lo = mid; else hi = mid;
         }
-        if (in) {
-            const int v = segbeg[seg] + (f - segoff[seg]);
-            cv = a.cell[v];
-            fu = a.frac[2 * (int64_t)v];
-            fv = a.frac[2 * (int64_t)v + 1];
-            val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
-        }
+        seg = lo;
+        v = segbeg[lo] + (f - segoff[lo]);
+        bnd = segoff[lo + 1];
+    };
+    auto load = [&]() {
+        cv = a.cell[v];
+        fu = a.frac[2 * (int64_t)v];
+        fv = a.frac[2 * (int64_t)v + 1];
+        val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
     };
     if (s_begin < s_end) {
-        // First slice: full search from the first segment.
         const int f = s_begin * 64 + lane;
         if (f < total) {
-            int lo = 0, hi = NS;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (segoff[mid] <= f) lo = mid; else hi = mid;
-            }
-            seg = lo;
+            locate(f, 0);
+            load();
         }
-        fetch(f);
     }
 
-    int ic[NB], jc[NB];
+    int ic[NB], jc[QB];
 #pragma unroll
-    for (int p = 0; p < NB; ++p) {
-        ic[p] = min(li + 8 * p, J - 1) * SR;
-        jc[p] = min(lj + 8 * p, J - 1) * SR;
-    }
-    // The open run: its cells' addresses in the private copy (lanes whose
-    // cell lies outside the owner tile use a trash cell of their own), the
-    // values read from there when the run opened, and the sum of its
-    // contributions so far.  Closing the run adds and stores; the read was
-    // issued when the run opened, so its latency hides behind the run.
-    C<R> acc[NB][NB], g[NB][NB];
-    int addr[NB][NB];
+    for (int p = 0; p < NB; ++p) ic[p] = min(li + 8 * p, J - 1) * SR;
+#pragma unroll
+    for (int q = 0; q < QB; ++q) jc[q] = (lj + 8 * q) * SR;
+    C<R> acc[NB][QB];
 #pragma unroll
     for (int p = 0; p < NB; ++p)
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            acc[p][q] = mk<R>(0, 0);
-            g[p][q] = mk<R>(0, 0);
-            addr[p][q] = O * OS + lane;
-        }
-    auto close_run = [&]() {
+        for (int q = 0; q < QB; ++q) acc[p][q] = mk<R>(0, 0);
+    // Closing a run adds its sums to the tile cells it covers inside the owner tile.
+    auto close_run = [&](int pos) {
+        const int la = (pos >> 8) - J, cb = ((pos & 255) << 3) - J;
 #pragma unroll
         for (int p = 0; p < NB; ++p)
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                g[p][q].x += acc[p][q].x;
-                g[p][q].y += acc[p][q].y;
-                mine[addr[p][q]] = g[p][q];
+            for (int q = 0; q < QB; ++q) {
+                const int i = li + 8 * p;
+                const int ra = la + i, rb = cb + lj + 8 * q;
+                if (i < J && (unsigned)ra < (unsigned)O && (unsigned)rb < (unsigned)O) {
+                    const int c = ra * OS + rb;
+                    __hip_atomic_fetch_add(tre + c, (double)acc[p][q].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(tim + c, (double)acc[p][q].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
                 acc[p][q] = mk<R>(0, 0);
             }
     };
-    auto open_run = [&](int pos) {
-        const int la = (pos >> 8) - J, lb = (pos & 255) - J;
+    // Matrix path: one 16 x 16 x 4 product per group of 4 staged entries,
+    // A[i][k] = component i % 2 of window row i / 2 of entry k (lane i + 16k),
+    // B[k][j] = column slot j of entry k (lane j + 16k); lane l then holds
+    // D[4 (l / 16) + r][l % 16], i.e. window rows 2 (l / 16) and 2 (l / 16) + 1
+    // (real, imaginary) of column slot l % 16.
+    typedef float mf4 __attribute__((ext_vector_type(4)));
+    mf4 dacc = {0.f, 0.f, 0.f, 0.f};
+    const int mk_ = lane >> 4, mi = lane & 15;
+    const int abase = 2 * ((mi >> 1) * SR + mk_) + (mi & 1);  // float index into wuv
+    const int bbase = mi * SR + mk_;                          // index into wv
+    auto close_run_mf = [&](int pos) {
+        const int la = (pos >> 8) - J, cb = ((pos & 255) << 3) - J;
+        const int rb = cb + mi;
 #pragma unroll
-        for (int p = 0; p < NB; ++p)
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int i = li + 8 * p, j = lj + 8 * q;
-                const int ra = la + i, rb = lb + j;
-                const bool ok = i < J && j < J && (unsigned)ra < (unsigned)O && (unsigned)rb < (unsigned)O;
-                addr[p][q] = ok ? ra * OS + rb : O * OS + lane;
+        for (int h = 0; h < 2; ++h) {
+            const int i = 2 * mk_ + h, ra = la + i;
+            if (i < J && (unsigned)ra < (unsigned)O && (unsigned)rb < (unsigned)O) {
+                const int c = ra * OS + rb;
+                __hip_atomic_fetch_add(tre + c, (double)dacc[2 * h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(tim + c, (double)dacc[2 * h + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-#pragma unroll
-        for (int p = 0; p < NB; ++p)
-#pragma unroll
-            for (int q = 0; q < NB; ++q) g[p][q] = mine[addr[p][q]];
+        }
+        dacc = mf4{0.f, 0.f, 0.f, 0.f};
     };
-    int cur = -1;  // packed cell of the open run (-1: none yet)
+    int cur = -1;  // packed window row and column block of the open run (-1: none yet)
 
     for (int sl = s_begin; sl < s_end; ++sl) {
         const int base = sl * 64;
@@ -507,8 +563,9 @@ __global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
         if (!live) val = mk<R>(0, 0);
         const int r = seg >> 1, piece = seg & 1;
         const int la = r - (J - 1);
-        const int lb = (int)(cv >> 16) % T + (piece ? len0 : -lc0) - (J - 1);
-        const int pos = live ? ((la + J) << 8) | (lb + J) : -1;
+        const int cb8 = (int)((cv >> 16) & (uint32_t)(T - 1)) + (piece ? len0 : -lc0) + 1;  // lb + J, in [1, O + J]
+        const int pos = live ? ((la + J) << 8) | (cb8 >> 3) : -1;
+        const int db = cb8 & 7;
         {
             R wu_[J], wv_[J];
             if constexpr (kScalarCoef) {
@@ -519,68 +576,124 @@ __global__ void __launch_bounds__(kOwnThreads) grid_owner(OwnerArgs<R> a) {
                 kb_weights_ptr<R, J>(fv, kcl, wv_);
             }
 #pragma unroll
-            for (int i = 0; i < J; ++i) {
-                wuv[i * SR + lane] = mk<R>(wu_[i] * val.x, wu_[i] * val.y);
-                wv[i * SR + lane] = wv_[i];
+            for (int i = 0; i < J; ++i) wuv[i * SR + lane] = mk<R>(wu_[i] * val.x, wu_[i] * val.y);
+            // Column weights at rows db .. db + J - 1, zeros in the other rows.
+#pragma unroll
+            for (int c = 0; c < NC - J; ++c) {
+                int row = db + J + c;
+                row = row >= NC ? row - NC : row;
+                wv[row * SR + lane] = R(0);
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) wv[(db + j) * SR + lane] = wv_[j];
+        }
+        // Run starts: entries whose window row or column block differs from
+        // the previous entry's (lane 0 compares with the open run).
+        const int prev = __builtin_amdgcn_update_dpp(cur, pos, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+        const uint64_t starts = __ballot(live && pos != prev);
+        __builtin_amdgcn_wave_barrier();
+        // The next slice's visibility: global loads in flight during the accumulation.
+        if (sl + 1 < s_end) {
+            const int f = base + 64 + lane;
+            if (f < total) {
+                if (f >= bnd) locate(f, seg + 1);
+                else v += 64;
+                load();
             }
         }
-        // Run starts: entries whose cell differs from the previous entry's.
-        int prev = __shfl_up(pos, 1);
-        if (lane == 0) prev = cur;
-        const uint64_t starts = __ballot(live && pos != prev);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (sl + 1 < s_end) fetch(base + 64 + lane);  // global loads in flight during the accumulation
 
-        // Accumulation: one staged visibility per step; unrolled over the
-        // slice (constant bit tests, immediate offsets) where registers allow.
-        auto batch = [&](int kb) {
-            C<R> us[BATCH][NB];
-            R ws[BATCH][NB];
+        if constexpr (MF) {
+            // Groups of 4 entries; a group holding run starts is split into
+            // products over the entries of each run (B masked by entry).
+            const float *wuf = reinterpret_cast<const float *>(wuv);
 #pragma unroll
-            for (int k = 0; k < BATCH; ++k)
-#pragma unroll
-                for (int p = 0; p < NB; ++p) {
-                    us[k][p] = wuv[ic[p] + kb + k];
-                    ws[k][p] = wv[jc[p] + kb + k];
-                }
-#pragma unroll
-            for (int k = 0; k < BATCH; ++k) {
-                if (__builtin_expect((starts >> (kb + k)) & 1, 0)) {
-                    if (cur >= 0) close_run();
-                    cur = __builtin_amdgcn_readlane(pos, kb + k);
-                    open_run(cur);
-                }
-#pragma unroll
-                for (int p = 0; p < NB; ++p)
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) {
-                        acc[p][q].x += us[k][p].x * ws[k][q];
-                        acc[p][q].y += us[k][p].y * ws[k][q];
+            for (int g = 0; g < 16; ++g) {
+                const float av = wuf[abase + 8 * g];
+                const float bv = wv[bbase + 4 * g];
+                const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;
+                if (__builtin_expect(s4 == 0, 1)) {
+                    dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc, 0, 0, 0);
+                } else {
+                    unsigned m = s4;
+                    int lo = 0;
+                    while (m) {
+                        const int b = __builtin_ctz(m);
+                        m &= m - 1;
+                        if (b > lo) {
+                            const float bm = (mk_ >= lo && mk_ < b) ? bv : 0.f;
+                            dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                        }
+                        if (cur >= 0) close_run_mf(cur);
+                        cur = __builtin_amdgcn_readlane(pos, 4 * g + b);
+                        lo = b;
                     }
+                    const float bm = mk_ >= lo ? bv : 0.f;
+                    dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                }
             }
-        };
-        if constexpr (kUnroll) {
-#pragma unroll
-            for (int kb = 0; kb < 64; kb += BATCH) batch(kb);
         } else {
-#pragma unroll 1
-            for (int kb = 0; kb < 64; kb += BATCH) batch(kb);
+        // Accumulation: one staged visibility per step; unrolled over the
+            // slice (constant bit tests, immediate offsets) where registers allow,
+            // with the reads of the next batch issued before the current batch is
+            // used.
+            auto fetch_batch = [&](int kb, C<R> (&us)[BATCH][NB], R (&ws)[BATCH][QB]) {
+    #pragma unroll
+                for (int k = 0; k < BATCH; ++k) {
+    #pragma unroll
+                    for (int p = 0; p < NB; ++p) us[k][p] = wuv[ic[p] + kb + k];
+    #pragma unroll
+                    for (int q = 0; q < QB; ++q) ws[k][q] = wv[jc[q] + kb + k];
+                }
+            };
+            auto use_batch = [&](int kb, const C<R> (&us)[BATCH][NB], const R (&ws)[BATCH][QB]) {
+    #pragma unroll
+                for (int k = 0; k < BATCH; ++k) {
+                    if (__builtin_expect((starts >> (kb + k)) & 1, 0)) {
+                        if (cur >= 0) close_run(cur);
+                        cur = __builtin_amdgcn_readlane(pos, kb + k);
+                    }
+    #pragma unroll
+                    for (int p = 0; p < NB; ++p)
+    #pragma unroll
+                        for (int q = 0; q < QB; ++q) {
+                            acc[p][q].x += us[k][p].x * ws[k][q];
+                            acc[p][q].y += us[k][p].y * ws[k][q];
+                        }
+                }
+            };
+            if constexpr (kUnroll) {
+                C<R> u0[BATCH][NB], u1[BATCH][NB];
+                R w0[BATCH][QB], w1[BATCH][QB];
+                fetch_batch(0, u0, w0);
+    #pragma unroll
+                for (int kb = 0; kb < 64; kb += 2 * BATCH) {
+                    fetch_batch(kb + BATCH, u1, w1);
+                    use_batch(kb, u0, w0);
+                    if (kb + 2 * BATCH < 64) fetch_batch(kb + 2 * BATCH, u0, w0);
+                    use_batch(kb + BATCH, u1, w1);
+                }
+            } else {
+    #pragma unroll 1
+                for (int kb = 0; kb < 64; kb += BATCH) {
+                    C<R> u0[BATCH][NB];
+                    R w0[BATCH][QB];
+                    fetch_batch(kb, u0, w0);
+                    use_batch(kb, u0, w0);
+                }
+            }
         }
         // The next slice's staging overwrites this one.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (cur >= 0) close_run();
+    if (cur >= 0) {
+        if constexpr (MF) close_run_mf(cur);
+        else close_run(cur);
+    }
     __syncthreads();
-    // Sum the private copies in wave order and store the tile.
+    // Store the tile.
     for (int c = tid; c < O * O; c += kOwnThreads) {
         const int r = c / O, col = c - r * O;
-        C<R> sum = priv[r * OS + col];
-        for (int w = 1; w < kOwnWaves; ++w) sum = cadd<R>(sum, priv[w * PS + r * OS + col]);
-        a.grid[(int64_t)(oa + r) * K + ob + col] = sum;
+        a.grid[(int64_t)(oa + r) * K + ob + col] = mk<R>((R)tre[r * OS + col], (R)tim[r * OS + col]);
     }
 }
 
@@ -696,9 +809,13 @@ template <typename R> static void build_layout_t(riop_plan *p, const void *uv, h
         }
         work[ot] = {w, ot};
     }
+    std::vector<int> count(nowner);
+    for (int ot = 0; ot < nowner; ++ot) count[ot] = (int)work[ot].first;
     std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
     std::vector<int> order(nowner);
     for (int t = 0; t < nowner; ++t) order[t] = work[t].second;
+    p->owner_count.alloc(sizeof(int) * nowner);
+    RIOP_HIP(hipMemcpyAsync(p->owner_count.ptr, count.data(), sizeof(int) * nowner, hipMemcpyHostToDevice, st));
     p->nowner = nowner;
     p->owner_order.alloc(sizeof(int) * nowner);
     RIOP_HIP(hipMemcpyAsync(p->owner_order.ptr, order.data(), sizeof(int) * nowner, hipMemcpyHostToDevice, st));
@@ -763,10 +880,11 @@ template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, 
 
 void choose_owner(riop_plan *p, int want_owner) {
     const bool f64 = p->prec == RIOP_F64;
-    const int O = want_owner ? want_owner : std::min(p->tile, f64 ? 16 : 32);
+    const int O = want_owner ? want_owner : std::min(p->tile, 32);
     RIOP_REQUIRE(O >= 8 && O <= p->tile && (O & (O - 1)) == 0, RIOP_EINVAL,
                  "grid_owner must be a power of two in [8, tile]");
-    const size_t lds = f64 ? owner_lds<double>(O, owner_stride(O), p->J) : owner_lds<float>(O, owner_stride(O), p->J);
+    const size_t lds = f64 ? owner_lds<double>(O, owner_stride(O), p->J, owner_waves<double>(p->J))
+                           : owner_lds<float>(O, owner_stride(O), p->J, owner_waves<float>(p->J));
     RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding owner tile too large for LDS");
     p->owner = O;
 }
@@ -780,6 +898,7 @@ static void launch_owner(riop_plan *p, const void *vals, int order_user, void *o
     a.perm = p->perm.as<int>();
     a.cell_start = p->cell_start.as<int>();
     a.order = p->owner_order.as<int>();
+    a.count = p->owner_count.as<int>();
     a.vin = static_cast<const C<R> *>(vals);
     a.kc = p->kcoef_owner.as<R>();
     a.K = p->K;
@@ -788,16 +907,17 @@ static void launch_owner(riop_plan *p, const void *vals, int order_user, void *o
     a.O = p->owner;
     a.OS = owner_stride(p->owner);
     a.ops = p->K / p->owner;
-    const size_t lds = owner_lds<R>(a.O, a.OS, p->J);
+    const int waves = owner_waves<R>(p->J);
+    const size_t lds = owner_lds<R>(a.O, a.OS, p->J, waves);
     RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding owner tile too large for LDS");
     TimedScope ts(p, KK_GRID, st);
     switch (p->J) {
 #define GK(JJ)                                                                                                    \
     case JJ:                                                                                                      \
         if (order_user)                                                                                           \
-            hipLaunchKernelGGL((grid_owner<R, JJ, true>), dim3(p->nowner), dim3(kOwnThreads), lds, st, a);       \
+            hipLaunchKernelGGL((grid_owner<R, JJ, true>), dim3(p->nowner), dim3(64 * waves), lds, st, a);       \
         else                                                                                                      \
-            hipLaunchKernelGGL((grid_owner<R, JJ, false>), dim3(p->nowner), dim3(kOwnThreads), lds, st, a);      \
+            hipLaunchKernelGGL((grid_owner<R, JJ, false>), dim3(p->nowner), dim3(64 * waves), lds, st, a);      \
         break;
         RIOP_J_CASES(GK)
 #undef GK

@@ -151,8 +151,13 @@ __device__ inline int band_index(int i, int N, int n) {
     return -1;
 }
 
+// Row passes run 256-thread blocks; bounding single-precision radix-2^k lines
+// to 8 blocks per CU (64 registers) lets all K lines of a 2048-point pass be
+// resident at once.  Wider register sets keep fewer blocks so they do not spill.
+template <typename R, int E> constexpr int fft_row_blocks() { return E == 8 ? (sizeof(R) == 4 ? 8 : 4) : 2; }
+
 template <typename R, int E, int SGN, bool COLS>
-__global__ void __launch_bounds__(1024) fft_pass(FftArgs<R> a) {
+__global__ void __launch_bounds__(COLS ? 1024 : 256, COLS ? 1 : (fft_row_blocks<R, E>())) fft_pass(FftArgs<R> a) {
     extern __shared__ unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
     const int N = a.N;
@@ -208,6 +213,83 @@ __global__ void __launch_bounds__(1024) fft_pass(FftArgs<R> a) {
         }
     }
 
+    if (!active) return;
+    const R tf_out = (a.dbt && !a.factors_at_input) ? a.dbt[t] : R(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = jt + e * NE;
+        const int j = a.crop_out ? band_index(i, N, a.n) : i;
+        if (j < 0) continue;
+        C<R> z = v[e];
+        if (!a.factors_at_input) {
+            R f = a.scale * tf_out;
+            if (a.dax) f *= a.dax[j];
+            z = cscale<R>(z, f);
+        }
+        a.out[t * a.out_ts + (long)j * a.out_es] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Power-of-two lengths, N = 2^LOGN, 16 <= N <= 16384: the same pass with the
+// stage sequence fixed at compile time (radix 8 while 8 divides what is left,
+// then one radix-4 or radix-2 stage), so every index, stride and twiddle step
+// is a constant and k = j mod Ns is a mask.
+
+template <typename R, int E, int SGN, int N, int Ns>
+__device__ inline void p2_stages(C<R> (&v)[E], int jt, C<R> *lds, int ls, const C<R> *tw) {
+    constexpr int rem = N / Ns;
+    constexpr int RR = rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
+    constexpr int NE = N / E;
+    stage<R, E, RR, SGN>(v, jt, NE, N, Ns, tw);
+    if constexpr (Ns * RR < N) {
+        exchange<R, E>(v, lds, ls, jt, NE, Ns, RR);
+        p2_stages<R, E, SGN, N, Ns * RR>(v, jt, lds, ls, tw);
+    }
+}
+
+template <typename R, int LOGN, int SGN, bool COLS>
+__global__ void __launch_bounds__(COLS ? 1024 : 256, COLS ? 1 : (fft_row_blocks<R, 8>()))
+fft_pass_p2(FftArgs<R> a) {
+    constexpr int N = 1 << LOGN, E = 8, NE = N / E;
+    extern __shared__ unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+    int c, jt;
+    if (COLS) {
+        c = threadIdx.x % a.C;
+        jt = threadIdx.x / a.C;
+    } else {
+        c = threadIdx.x / NE;
+        jt = threadIdx.x % NE;
+    }
+    int blk = blockIdx.x;
+    if (COLS) {  // contiguous transform ranges per XCD (blocks are dealt round-robin to the 8 XCDs)
+        const int nb = gridDim.x, qq = nb >> 3, rr = nb & 7, x = blk & 7;
+        blk = x * qq + min(x, rr) + (blk >> 3);
+    }
+    const long t = (long)blk * a.C + c;
+    const bool active = t < a.nbatch;
+    C<R> *lds = COLS ? smem + c : smem + (long)c * N;
+    const int ls = COLS ? a.C : 1;
+
+    C<R> v[E];
+    const R tf = (active && a.dbt && a.factors_at_input) ? a.dbt[t] : R(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = jt + e * NE;
+        const int j = a.pad_in ? band_index(i, N, a.n) : i;
+        C<R> z = mk<R>(0, 0);
+        if (active && j >= 0) {
+            z = a.in[t * a.in_ts + (long)j * a.in_es];
+            if (a.factors_at_input) {
+                R f = a.scale * tf;
+                if (a.dax) f *= a.dax[j];
+                z = cscale<R>(z, f);
+            }
+        }
+        v[e] = z;
+    }
+    p2_stages<R, E, SGN, N, 1>(v, jt, lds, ls, a.tw);
     if (!active) return;
     const R tf_out = (a.dbt && !a.factors_at_input) ? a.dbt[t] : R(1);
 #pragma unroll
@@ -294,16 +376,29 @@ static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
         Cb = std::max(1, 256 / NE);
         Cb = (int)std::max<size_t>(1, std::min<size_t>(Cb, lds_budget / line));
     }
+    RIOP_REQUIRE(COLS || Cb * NE <= 256, RIOP_ENOTSUP, "FFT row block too large");
     a.C = Cb;
     const int threads = Cb * NE;
     RIOP_REQUIRE(threads <= 1024, RIOP_ENOTSUP, "FFT block too large");
     const int blocks = (a.nbatch + Cb - 1) / Cb;
     const size_t lds = line * Cb;
     TimedScope ts(p, kind, st);
-    if (E == 8)
+    const int N = f.N;
+    const bool pow2 = (N & (N - 1)) == 0 && N >= 16 && N <= 16384;
+    if (pow2 && E == 8) {
+        switch (N) {
+#define P2(LG)                                                                                        \
+    case 1 << LG:                                                                                     \
+        hipLaunchKernelGGL((fft_pass_p2<R, LG, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a); \
+        break;
+            P2(4) P2(5) P2(6) P2(7) P2(8) P2(9) P2(10) P2(11) P2(12) P2(13) P2(14)
+#undef P2
+        }
+    } else if (E == 8) {
         hipLaunchKernelGGL((fft_pass<R, 8, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a);
-    else
+    } else {
         hipLaunchKernelGGL((fft_pass<R, 24, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a);
+    }
     RIOP_HIP(hipGetLastError());
 }
 

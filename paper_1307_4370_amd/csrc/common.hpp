@@ -123,6 +123,8 @@ struct SdmmWork {
     DevBuf z1loc, w1;       // q*N complex
     DevBuf ysort, z2loc, s2; // M complex, plan order
     DevBuf partials;        // doubles for block reductions
+    DevBuf f1part;          // per analysis block partials of f1 (psi_adj_blocks doubles)
+    int f1_count = 0;
     DevBuf scalars;         // doubles: scalar slots
     DevBuf history;         // doubles, 4 per iteration
     int hist_cap = 0;       // iterations the history buffer holds
@@ -220,8 +222,10 @@ template <typename R> struct Prox1 {
     C<R> *w1;          // r1 - z1 (new), input of the synthesis
     const R *weights;  // diagonal of W, nullable (W = I)
     const double *gamma;
-    double *f1_acc;    // accumulates f1 = sum w |Psi^dagger x|
+    double *f1_part;   // one partial of f1 = sum w |Psi^dagger x| per analysis block
 };
+// Number of analysis blocks (all levels and the Dirac plane) of one Psi^dagger.
+int psi_adj_blocks(const riop_plan *p);
 template <typename R>
 void launch_psi_adj_prox(riop_plan *p, const void *x, const Prox1<R> &px, hipStream_t st);
 

@@ -60,7 +60,9 @@ __device__ inline void emit_coef(const AnaArgs<R> &a, long j, C<R> c, double &f1
     f1 += (double)w * sqrt((double)c.x * c.x + (double)c.y * c.y);
 }
 
-template <typename R> __device__ inline void block_add_f1(double f1, double *acc) {
+// Block sum of f1 into this block's own partial slot (no atomics; the
+// consumer adds the slots in a fixed order).
+template <typename R> __device__ inline void block_add_f1(double f1, double *part) {
     __shared__ double red[256];
     red[threadIdx.x] = f1;
     __syncthreads();
@@ -68,80 +70,160 @@ template <typename R> __device__ inline void block_add_f1(double f1, double *acc
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) unsafeAtomicAdd(acc, red[0]);
+    if (threadIdx.x == 0) part[(long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
+// Prox epilogue with its operands already loaded (see emit_coef).
 template <typename R>
+__device__ inline void emit_coef_pre(const AnaArgs<R> &a, long j, C<R> c, C<R> z, R w, double &f1) {
+    c = cscale<R>(c, a.scale);
+    if (!a.prox) {
+        a.alpha[j] = c;
+        return;
+    }
+    const R lam = (R)(*a.px.gamma) * w;
+    const C<R> v = cadd<R>(c, z);
+    const R mag = sqrt(v.x * v.x + v.y * v.y);
+    const R sc = mag > lam ? R(1) - lam / mag : R(0);
+    const C<R> r = cscale<R>(v, sc);
+    const C<R> zn = csub<R>(v, r);
+    a.px.z1[j] = zn;
+    a.px.w1[j] = csub<R>(r, zn);
+    f1 += (double)w * sqrt((double)c.x * c.x + (double)c.y * c.y);
+}
+
+// One level of the analysis for one basis (blockIdx.y) and one TO x TO tile
+// of each sub-band (blockIdx.x); 256 threads, seen as 4 rows of 64.
+template <typename R, int TO>
 __global__ void __launch_bounds__(256) dwt_analysis(AnaArgs<R> a) {
     extern __shared__ unsigned char smem_raw[];
     const int bi = blockIdx.y;
     const int b = a.basis[bi];
     const int Lf = 2 * b;
-    const R *h = a.filt + (b * 2 + 0) * kMaxTaps;
-    const R *g = a.filt + (b * 2 + 1) * kMaxTaps;
-    const int s = a.s, half = s >> 1, TO = a.TO;
+    // Filter taps, zero past Lf: single precision keeps them in (scalar)
+    // registers; double precision would need 64 scalar registers for them and
+    // reads an LDS copy instead.
+    __shared__ R taps[2][kMaxTaps];
+    R h[kMaxTaps], g[kMaxTaps];
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int m = 0; m < kMaxTaps; ++m) {
+            h[m] = m < Lf ? a.filt[(b * 2 + 0) * kMaxTaps + m] : R(0);
+            g[m] = m < Lf ? a.filt[(b * 2 + 1) * kMaxTaps + m] : R(0);
+        }
+    } else {
+        if (threadIdx.x < 2 * kMaxTaps) {
+            const int e = threadIdx.x / kMaxTaps, m = threadIdx.x % kMaxTaps;
+            taps[e][m] = m < Lf ? a.filt[(b * 2 + e) * kMaxTaps + m] : R(0);
+        }
+    }
+#define TAP_H(m) (sizeof(R) == 4 ? h[m] : taps[0][m])
+#define TAP_G(m) (sizeof(R) == 4 ? g[m] : taps[1][m])
+    const int s = a.s, half = s >> 1;
     const int tiles = half / TO;
     const int k0 = (blockIdx.x / tiles) * TO, l0 = (blockIdx.x % tiles) * TO;
     const int IR = 2 * TO + Lf - 2;
-    C<R> *reg = reinterpret_cast<C<R> *>(smem_raw);
-    C<R> *rlo = reg + IR * IR;
-    C<R> *rhi = rlo + IR * TO;
+    constexpr int IRM = 2 * TO + kMaxTaps - 2;  // LDS row stride
+    C<R> *reg = reinterpret_cast<C<R> *>(smem_raw);  // [IRM][IRM]
+    C<R> *rlo = reg + IRM * IRM;                     // [IRM][TO]
+    C<R> *rhi = rlo + IRM * TO;
     const C<R> *in = a.in + bi * a.in_bstride;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 
-    for (int idx = threadIdx.x; idx < IR * IR; idx += blockDim.x) {
-        const int r = idx / IR, c = idx - r * IR;
-        const int gr = (2 * k0 + r) % s, gc = (2 * l0 + c) % s;
-        reg[idx] = in[(long)gr * s + gc];
+    // Prox operands of this thread's outputs, loaded before the filtering.
+    const int n = a.n;
+    const long pbase = (long)a.plane[bi] * n * n;
+    constexpr int PER = (TO * TO + 255) / 256;
+    C<R> zq[PER][4];
+    R wq[PER][4];
+    long jq[PER][4];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + 256 * u;
+        const int k = idx / TO, l = idx % TO;  // TO is a constant power of two
+        const int gk = k0 + k, gl = l0 + l;
+        jq[u][0] = pbase + (long)gk * n + gl;
+        jq[u][1] = pbase + (long)gk * n + half + gl;
+        jq[u][2] = pbase + (long)(half + gk) * n + gl;
+        jq[u][3] = pbase + (long)(half + gk) * n + half + gl;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            zq[u][t] = mk<R>(0, 0);
+            wq[u][t] = R(1);
+        }
+        if (a.prox && idx < TO * TO) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t == 0 && !a.last) continue;  // LL goes to the next level
+                zq[u][t] = a.px.z1[jq[u][t]];
+                if (a.px.weights) wq[u][t] = a.px.weights[jq[u][t]];
+            }
+        }
+    }
+
+    // Periodic extension; on the smallest levels the region can exceed 2s.
+    for (int r = ty; r < IR; r += 4) {
+        int gr = 2 * k0 + r;
+        while (gr >= s) gr -= s;
+        for (int c = tx; c < IR; c += 64) {
+            int gc = 2 * l0 + c;
+            while (gc >= s) gc -= s;
+            reg[r * IRM + c] = in[(long)gr * s + gc];
+        }
     }
     __syncthreads();
     // Rows (axis 1): rlo[r][l] = sum_m h[m] in[r][2l + m], rhi with g.
-    for (int idx = threadIdx.x; idx < IR * TO; idx += blockDim.x) {
-        const int r = idx / TO, l = idx - r * TO;
+    for (int idx = threadIdx.x; idx < IR * TO; idx += 256) {
+        const int r = idx / TO, l = idx % TO;
         R lr = 0, li = 0, hr = 0, hi = 0;
-        const C<R> *row = reg + r * IR + 2 * l;
-        for (int m = 0; m < Lf; ++m) {
-            const C<R> v = row[m];
-            lr += h[m] * v.x;
-            li += h[m] * v.y;
-            hr += g[m] * v.x;
-            hi += g[m] * v.y;
+        const C<R> *row = reg + r * IRM + 2 * l;
+#pragma unroll
+        for (int m = 0; m < kMaxTaps; ++m) {
+            if (m < Lf) {
+                const C<R> v = row[m];
+                lr += TAP_H(m) * v.x;
+                li += TAP_H(m) * v.y;
+                hr += TAP_G(m) * v.x;
+                hi += TAP_G(m) * v.y;
+            }
         }
-        rlo[idx] = mk<R>(lr, li);
-        rhi[idx] = mk<R>(hr, hi);
+        rlo[r * TO + l] = mk<R>(lr, li);
+        rhi[r * TO + l] = mk<R>(hr, hi);
     }
     __syncthreads();
     // Columns (axis 0).
     double f1 = 0.0;
-    C<R> *alpha = a.alpha + (long)a.plane[bi] * a.n * a.n;
-    const long pbase = (long)a.plane[bi] * a.n * a.n;
-    for (int idx = threadIdx.x; idx < TO * TO; idx += blockDim.x) {
-        const int k = idx / TO, l = idx - k * TO;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + 256 * u;
+        if (idx >= TO * TO) break;
+        const int k = idx / TO, l = idx % TO;
         R llr = 0, lli = 0, hlr = 0, hli = 0, lhr = 0, lhi = 0, hhr = 0, hhi = 0;
-        for (int m = 0; m < Lf; ++m) {
-            const C<R> vl = rlo[(2 * k + m) * TO + l];
-            const C<R> vh = rhi[(2 * k + m) * TO + l];
-            llr += h[m] * vl.x;
-            lli += h[m] * vl.y;
-            hlr += g[m] * vl.x;
-            hli += g[m] * vl.y;
-            lhr += h[m] * vh.x;
-            lhi += h[m] * vh.y;
-            hhr += g[m] * vh.x;
-            hhi += g[m] * vh.y;
+#pragma unroll
+        for (int m = 0; m < kMaxTaps; ++m) {
+            if (m < Lf) {
+                const C<R> vl = rlo[(2 * k + m) * TO + l];
+                const C<R> vh = rhi[(2 * k + m) * TO + l];
+                llr += TAP_H(m) * vl.x;
+                lli += TAP_H(m) * vl.y;
+                hlr += TAP_G(m) * vl.x;
+                hli += TAP_G(m) * vl.y;
+                lhr += TAP_H(m) * vh.x;
+                lhi += TAP_H(m) * vh.y;
+                hhr += TAP_G(m) * vh.x;
+                hhi += TAP_G(m) * vh.y;
+            }
         }
         const int gk = k0 + k, gl = l0 + l;
-        const int n = a.n;
-        if (a.last) {
-            emit_coef<R>(a, pbase + (long)gk * n + gl, mk<R>(llr, lli), f1);
-        } else {
-            a.ll_out[bi * a.ll_bstride + (long)gk * half + gl] = mk<R>(llr, lli);
-        }
-        emit_coef<R>(a, pbase + (long)gk * n + half + gl, mk<R>(lhr, lhi), f1);
-        emit_coef<R>(a, pbase + (long)(half + gk) * n + gl, mk<R>(hlr, hli), f1);
-        emit_coef<R>(a, pbase + (long)(half + gk) * n + half + gl, mk<R>(hhr, hhi), f1);
+        if (a.last) emit_coef_pre<R>(a, jq[u][0], mk<R>(llr, lli), zq[u][0], wq[u][0], f1);
+        else a.ll_out[bi * a.ll_bstride + (long)gk * half + gl] = mk<R>(llr, lli);
+        emit_coef_pre<R>(a, jq[u][1], mk<R>(lhr, lhi), zq[u][1], wq[u][1], f1);
+        emit_coef_pre<R>(a, jq[u][2], mk<R>(hlr, hli), zq[u][2], wq[u][2], f1);
+        emit_coef_pre<R>(a, jq[u][3], mk<R>(hhr, hhi), zq[u][3], wq[u][3], f1);
     }
-    (void)alpha;
-    if (a.prox) block_add_f1<R>(f1, a.px.f1_acc);
+    if (a.prox) block_add_f1<R>(f1, a.px.f1_part);
+#undef TAP_H
+#undef TAP_G
 }
 
 // Dirac plane: alpha_0 = x / sqrt(q) (or its prox epilogue).
@@ -151,7 +233,7 @@ template <typename R> __global__ void dirac_analysis(AnaArgs<R> a, const C<R> *x
     const long base = (long)a.plane[0] * N;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
         emit_coef<R>(a, base + i, x[i], f1);
-    if (a.prox) block_add_f1<R>(f1, a.px.f1_acc);
+    if (a.prox) block_add_f1<R>(f1, a.px.f1_part);
 }
 
 template <typename R> struct SynArgs {
@@ -298,6 +380,23 @@ static size_t ll_offset(int n, int level) {
     return off;
 }
 
+static int dirac_blocks(int n) { return (int)std::min<long>(((long)n * n + 255) / 256, 4096); }
+
+int psi_adj_blocks(const riop_plan *p) {
+    const int n = p->n;
+    int nb = 0, total = 0;
+    for (int i = 0; i < p->q; ++i) {
+        if (p->bases[i] == 0) total += dirac_blocks(n);
+        else ++nb;
+    }
+    if (nb == 0) return total;
+    for (int lev = 1; lev <= p->L; ++lev) {
+        const int half = (n >> (lev - 1)) >> 1, tiles = half / tile_side(half);
+        total += tiles * tiles * nb;
+    }
+    return total;
+}
+
 template <typename R> static size_t ana_lds(int TO) {
     const int IR = 2 * TO + kMaxTaps - 2;
     return sizeof(C<R>) * (size_t)(IR * IR + 2 * IR * TO);
@@ -330,11 +429,11 @@ static void psi_adj_impl(riop_plan *p, const void *x, void *alpha, const Prox1<R
     if (dirac_plane >= 0) {
         AnaArgs<R> d = a;
         d.plane[0] = dirac_plane;
-        const long N = (long)n * n;
-        const int blocks = (int)std::min<long>((N + 255) / 256, 4096);
+        const int blocks = dirac_blocks(n);
         TimedScope ts(p, KK_PSI_ADJ, st);
         hipLaunchKernelGGL(dirac_analysis<R>, dim3(blocks), dim3(256), 0, st, d, static_cast<const C<R> *>(x));
         RIOP_HIP(hipGetLastError());
+        if (a.prox) a.px.f1_part += blocks;
     }
     if (nb == 0) return;
     C<R> *ll = p->ll.as<C<R>>();
@@ -354,7 +453,16 @@ static void psi_adj_impl(riop_plan *p, const void *x, void *alpha, const Prox1<R
         a.ll_bstride = (long)p->ll_stride;
         const int tiles = half / a.TO;
         TimedScope ts(p, KK_PSI_ADJ, st);
-        hipLaunchKernelGGL(dwt_analysis<R>, dim3(tiles * tiles, nb), dim3(256), ana_lds<R>(a.TO), st, a);
+        const dim3 grid(tiles * tiles, nb);
+        AnaArgs<R> al = a;
+        a.px.f1_part += a.prox ? (long)tiles * tiles * nb : 0;
+        switch (al.TO) {
+            case 16: hipLaunchKernelGGL((dwt_analysis<R, 16>), grid, dim3(256), ana_lds<R>(16), st, al); break;
+            case 8: hipLaunchKernelGGL((dwt_analysis<R, 8>), grid, dim3(256), ana_lds<R>(8), st, al); break;
+            case 4: hipLaunchKernelGGL((dwt_analysis<R, 4>), grid, dim3(256), ana_lds<R>(4), st, al); break;
+            case 2: hipLaunchKernelGGL((dwt_analysis<R, 2>), grid, dim3(256), ana_lds<R>(2), st, al); break;
+            default: hipLaunchKernelGGL((dwt_analysis<R, 1>), grid, dim3(256), ana_lds<R>(1), st, al); break;
+        }
         RIOP_HIP(hipGetLastError());
     }
 }

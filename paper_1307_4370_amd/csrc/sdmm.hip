@@ -239,12 +239,24 @@ template <typename R> __global__ void add3(const C<R> *a, const C<R> *b, const C
 
 // history[t] = {f1, zeta, nu, final CG rr} with t the device iteration
 // counter (so a captured graph can be replayed); f1_prev <- f1; t <- t + 1.
-__global__ void record_stats(const double *partials, double *scalars, double *hist, int cap, int rr_slot) {
+__global__ void record_stats(const double *partials, double *scalars, double *hist, int cap, int rr_slot,
+                             const double *f1part, int f1_count) {
     const double nu2 = slot_sum(partials, SLOT_NU);
     const double rr = slot_sum(partials, rr_slot);
+    // f1: the analysis blocks' partials, added in a fixed order.
+    __shared__ double red[kRedThreads];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < f1_count; i += kRedThreads) v += f1part[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         const int t = (int)scalars[SC_ITER];
-        const double f1 = scalars[SC_F1ACC];
+        const double f1 = red[0];
+        scalars[SC_F1ACC] = f1;
         const double prev = scalars[SC_F1PREV];
         const double zeta = prev == 0.0 ? INFINITY : fabs(f1 - prev) / fabs(prev);
         if (t < cap) {
@@ -291,6 +303,8 @@ static void ensure_work(riop_plan *p) {
     w.z2loc.alloc(cb * M);
     w.s2.alloc(cb * M);
     w.partials.alloc(sizeof(double) * kSlots * kRedBlocks);
+    w.f1_count = psi_adj_blocks(p);
+    w.f1part.alloc(sizeof(double) * (size_t)std::max(1, w.f1_count));
     w.scalars.alloc(sizeof(double) * kScalars);
     w.ready = true;
 }
@@ -410,13 +424,12 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
     double *sc = w.scalars.as<double>();
     C<R> *xh = w.xhat.as<C<R>>();
     Prox1<R> px{w.z1loc.as<C<R>>(), w.w1.as<C<R>>(), static_cast<const R *>(w.weights), sc + SC_GAMMA,
-                sc + SC_F1ACC};
+                w.f1part.as<double>()};
     for (int t = 0; t < iters; ++t) {
         // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x.
         int rr_slot = SLOT_RR0;
         cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
-        VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1ACC, 0.0);
         launch_psi_adj_prox<R>(p, xh, px, s);
         launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
         // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2).
@@ -433,7 +446,7 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         VEC_LAUNCH(p, prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(), w.x1.as<C<R>>(),
                    w.tmpN.as<C<R>>(), w.rhs.as<C<R>>(), N);
         VEC_LAUNCH(p, record_stats, dim3(1), RT(), 0, s, (const double *)part, sc, w.history.as<double>(),
-                   w.hist_cap, rr_slot);
+                   w.hist_cap, rr_slot, (const double *)w.f1part.as<double>(), w.f1_count);
         RIOP_HIP(hipGetLastError());
     }
 }

@@ -14,10 +14,15 @@ Psi^dagger / Psi pair).  value = visibilities through Phi + Phi^dagger per
 second = M x 18 pairs x steps / time.  Inputs are resident in HBM before the
 timed region.  FP32 storage and arithmetic with FP64 norms and CG scalars.
 
+The SDMM iterations are timed twice on the same plan and data: enqueued as
+stream launches (riop_sdmm), and as a one-channel batch whose iterations are
+one captured HIP graph replayed (riop_batch_sdmm); the faster is `value` and
+`config.launch` says which.  Neither timed region records timing events;
+per-kernel times and the roofline of the dominant kernel come from a separate
+short run with HIP events on the library's stream.
+
 Also reported: SDMM iterations/s, the same in plain FP64, stand-alone
-Phi + Phi^dagger pair throughput, per-kernel times and the roofline of the
-dominant kernel (HIP events on the library's stream), and the CPU oracle on a
-bounded sample.
+Phi + Phi^dagger pair throughput, and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -105,6 +110,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,7 +122,7 @@ def main():
     import torch
 
     import workloads as W
-    from paper_1307_4370_amd import Plan, noise_bound
+    from paper_1307_4370_amd import Batch, Plan, noise_bound
 
     c = W.C3
     n, M, J, L, ncg = c.n, c.M, c.J, c.levels, args.n_cg
@@ -145,19 +151,44 @@ def main():
     x, st, _, state = plan.sdmm(y, eps, T=args.warmup, n_cg=ncg)
     gamma = st["gamma"]
     torch.cuda.synchronize()
-    plan.timing(True)
-    torch.cuda.synchronize()
+    # (1) stream launches, no timing events in the timed region.
     t0 = time.perf_counter()
     x, st, hist, state = plan.sdmm(y, eps, T=args.steps, n_cg=ncg, gamma=gamma, x0=x, state=state)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_stream = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"fp32 stream launches: {ms_stream:.3f} ms/iteration, nu={st['nu']:.4f}")
+    # (2) per-kernel times from HIP events on the library stream (separate run).
+    ev_steps = max(1, min(args.steps, 3))
+    plan.timing(True)
+    torch.cuda.synchronize()
+    plan.sdmm(y, eps, T=ev_steps, n_cg=ncg, gamma=gamma, x0=x, state=state)
+    torch.cuda.synchronize()
     kernels = plan.timing_read()
     plan.timing(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    # (3) the same solve as a one-channel batch: one captured HIP graph of
+    # `steps` iterations, replayed; iteration time = (t(2 steps) - t(steps)) / steps.
+    ms_graph = None
+    if not args.no_graph:
+        bt = Batch([(n, plan._uv)], J=J, levels=L, prec="f32", autotune=False)
+        bt.sdmm([y], [eps], T=args.steps, n_cg=ncg, gamma=gamma, iters_per_graph=args.steps)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        bt.sdmm([y], [eps], T=args.steps, n_cg=ncg, gamma=gamma, iters_per_graph=args.steps)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        bt.sdmm([y], [eps], T=2 * args.steps, n_cg=ncg, gamma=gamma, iters_per_graph=args.steps)
+        torch.cuda.synchronize()
+        c2 = time.perf_counter()
+        ms_graph = ((c2 - b) - (b - a)) * 1e3 / args.steps
+        log(f"fp32 graph replay: {ms_graph:.3f} ms/iteration")
+        bt.close()
+        del bt
+    ms_step = min(ms_stream, ms_graph) if ms_graph else ms_stream
+    launch = "hip graph replay" if ms_graph and ms_graph <= ms_stream else "stream launches"
     pairs_per_step = ncg + 2
     value = M * pairs_per_step / (ms_step * 1e-3)
     iters_s = 1e3 / ms_step
-    log(f"fp32: {ms_step:.3f} ms/iteration, {value:.4g} vis/s, nu={st['nu']:.4f}")
+    log(f"fp32: {ms_step:.3f} ms/iteration ({launch}), {value:.4g} vis/s")
 
     # Roofline of the dominant kernel (largest total time in the timed region).
     cb = 8
@@ -221,8 +252,11 @@ def main():
         "config": {"workload": (f"{c.name}: {n}x{n} sky, M={M} Gaussian-density (u,v), oversampling 2, "
                                 f"KB J={J}, SARA Dirac+Db1-8 at {L} levels, one SDMM iteration per step "
                                 f"with n_cg={ncg}"),
-                   "n": n, "M": M, "J": J, "levels": L, "n_cg": ncg, "pairs_per_step": pairs_per_step},
+                   "n": n, "M": M, "J": J, "levels": L, "n_cg": ncg, "pairs_per_step": pairs_per_step,
+                   "launch": launch},
         "sdmm_iters_per_s": round(iters_s, 3),
+        "ms_per_step_stream": round(ms_stream, 4),
+        "ms_per_step_graph": round(ms_graph, 4) if ms_graph else None,
         "pair_visibilities_per_s": pairs32,
         "fp64": fp64,
         "roofline": roofline,

@@ -249,17 +249,18 @@ template <typename R> struct GridArgs {
     int order_user;
 };
 
-constexpr int kUnit = 2048;           // visibilities per work unit
+constexpr int kUnit = 1024;           // visibilities per work unit
 constexpr int kDegridThreads = 256;
 constexpr int kPerThread = kUnit / kDegridThreads;
 
 template <typename R, int J, bool USER>
 __device__ inline void degrid_one(const GridArgs<R> &a, const C<R> *reg, int W, int ta, int tb, int v) {
     const uint32_t cv = a.cell[v];
+    const R fu = a.frac[2 * (int64_t)v], fv = a.frac[2 * (int64_t)v + 1];
     const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;
     R wu_[J], wv_[J];
-    kb_weights<R, J>(a.frac[2 * (int64_t)v], a.kc, wu_);
-    kb_weights<R, J>(a.frac[2 * (int64_t)v + 1], a.kc, wv_);
+    kb_weights<R, J>(fu, a.kc, wu_);
+    kb_weights<R, J>(fv, a.kc, wv_);
     R ar = 0, ai = 0;
     const C<R> *base = reg + la * W + lb;
 #pragma unroll
@@ -291,12 +292,15 @@ __global__ void __launch_bounds__(kDegridThreads) degrid_kernel(GridArgs<R> a) {
     const int W = a.T + J - 1;
     const int ta = (wu.tile / a.tps) * a.T, tb = (wu.tile % a.tps) * a.T;
     const int K = a.K;
-    for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-        const int i = idx / W, j = idx - (idx / W) * W;
-        int gi = ta + i, gj = tb + j;
+    // Region rows by wavefront, columns by lane (no divisions).
+    for (int i = threadIdx.x >> 6; i < W; i += kDegridThreads >> 6) {
+        int gi = ta + i;
         if (gi >= K) gi -= K;
-        if (gj >= K) gj -= K;
-        reg[idx] = a.grid[(int64_t)gi * K + gj];
+        for (int j = threadIdx.x & 63; j < W; j += 64) {
+            int gj = tb + j;
+            if (gj >= K) gj -= K;
+            reg[i * W + j] = a.grid[(int64_t)gi * K + gj];
+        }
     }
     __syncthreads();
     const int end = wu.start + wu.count;

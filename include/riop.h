@@ -78,10 +78,8 @@ enum { RIOP_F32 = 1, RIOP_F64 = 2 };
  *              norms, dot products and CG scalars; RIOP_F64: double throughout
  *   tile       gridding tile side in grid cells (power of two, 8..64, dividing
  *              K = 2n); 0 selects the library's choice
- *   grid_owner side of the grid tile one gridding workgroup owns and writes
- *              (power of two, 8..tile); 0 selects the library's choice
- * Tuning fields change speed only: results do not depend on tile or
- * grid_owner beyond floating-point summation order.
+ * The tile changes speed only: results do not depend on it beyond
+ * floating-point summation order.
  */
 typedef struct {
     int32_t n;
@@ -92,8 +90,7 @@ typedef struct {
     uint32_t dict_mask;
     int32_t prec;
     int32_t tile;
-    int32_t grid_owner;
-    int32_t reserved[6];  /* must be zero */
+    int32_t reserved[7];  /* must be zero */
 } riop_desc;
 
 /* Read-only facts about a plan, filled by riop_plan_info. */
@@ -107,7 +104,6 @@ typedef struct {
     double kb_beta;         /* Kaiser-Bessel shape parameter */
     double kernel_fit_err;  /* max |polynomial - kernel| found at plan time */
     int64_t device_bytes;   /* device memory held by the plan */
-    int32_t grid_owner;     /* owner tile side used by gridding */
 } riop_info;
 
 /* Create a plan for one coverage.

@@ -40,8 +40,7 @@ class RiopError(RuntimeError):
 class Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("oversample", ctypes.c_int32), ("M", ctypes.c_int64),
                 ("J", ctypes.c_int32), ("levels", ctypes.c_int32), ("dict_mask", ctypes.c_uint32),
-                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32), ("grid_owner", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class Info(ctypes.Structure):
@@ -50,7 +49,7 @@ class Info(ctypes.Structure):
                 ("M", ctypes.c_int64), ("tile", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("nunits", ctypes.c_int32), ("kernel_degree", ctypes.c_int32),
                 ("kb_beta", ctypes.c_double), ("kernel_fit_err", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64), ("grid_owner", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64)]
 
 
 class SdmmParams(ctypes.Structure):
@@ -138,8 +137,7 @@ class Plan:
     """
 
     def __init__(self, n: int, uv: torch.Tensor, J: int = 8, levels: int = 4,
-                 dict_mask: int = FULL_MASK, prec: str = "f32", tile: int = 0, stream=None,
-                 grid_owner: int = 0):
+                 dict_mask: int = FULL_MASK, prec: str = "f32", tile: int = 0, stream=None):
         self.prec = prec
         self.rdtype = torch.float32 if prec == "f32" else torch.float64
         self.cdtype = torch.complex64 if prec == "f32" else torch.complex128
@@ -150,7 +148,7 @@ class Plan:
         self.n, self.M, self.J, self.levels = n, uv.shape[0], J, levels
         self.q = bin(dict_mask).count("1")
         d = Desc(n=n, oversample=2, M=self.M, J=J, levels=levels, dict_mask=dict_mask,
-                 prec=RIOP_F32 if prec == "f32" else RIOP_F64, tile=tile, grid_owner=grid_owner)
+                 prec=RIOP_F32 if prec == "f32" else RIOP_F64, tile=tile)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().riop_plan_create(ctypes.byref(d), uv.data_ptr(), _stream(stream), ctypes.byref(h)))

@@ -189,12 +189,12 @@ void build_kernel_tables(riop_plan *p) {
     for (int jp = 0; jp < J / 2; ++jp)
         for (int e = 0; e < 2; ++e)
             for (int k = 0; k < KS; ++k) compact[(size_t)(jp * 2 + e) * KS + k] = coef[(size_t)(jp * 2 + e) * kMaxPoly + k];
-    p->kcoef_owner.alloc(rb * compact.size());
+    p->kcoef_compact.alloc(rb * compact.size());
     if (p->prec == RIOP_F64) {
-        RIOP_HIP(hipMemcpy(p->kcoef_owner.ptr, compact.data(), rb * compact.size(), hipMemcpyHostToDevice));
+        RIOP_HIP(hipMemcpy(p->kcoef_compact.ptr, compact.data(), rb * compact.size(), hipMemcpyHostToDevice));
     } else {
         std::vector<float> c32(compact.begin(), compact.end());
-        RIOP_HIP(hipMemcpy(p->kcoef_owner.ptr, c32.data(), rb * c32.size(), hipMemcpyHostToDevice));
+        RIOP_HIP(hipMemcpy(p->kcoef_compact.ptr, c32.data(), rb * c32.size(), hipMemcpyHostToDevice));
     }
     p->kcoef.alloc(rb * coef.size());
     p->deapod.alloc(rb * n);
@@ -348,7 +348,7 @@ static void validate(const riop_desc *d) {
     RIOP_REQUIRE(d->n % (1 << d->levels) == 0, RIOP_ESHAPE, "n must be divisible by 2^levels");
     RIOP_REQUIRE(d->dict_mask != 0 && d->dict_mask < (1u << 9), RIOP_EINVAL, "dict_mask must be in [1, 2^9)");
     RIOP_REQUIRE(d->prec == RIOP_F32 || d->prec == RIOP_F64, RIOP_EINVAL, "prec must be RIOP_F32 or RIOP_F64");
-    for (int i = 0; i < 6; ++i) RIOP_REQUIRE(d->reserved[i] == 0, RIOP_EINVAL, "reserved fields must be zero");
+    for (int i = 0; i < 7; ++i) RIOP_REQUIRE(d->reserved[i] == 0, RIOP_EINVAL, "reserved fields must be zero");
     if (d->tile) {
         const int t = d->tile;
         RIOP_REQUIRE(t >= 8 && t <= 64 && (t & (t - 1)) == 0 && (2 * d->n) % t == 0, RIOP_EINVAL,
@@ -424,7 +424,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
             RIOP_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
             p->lds_max = (size_t)std::max(v, 0);
         }
-        choose_owner(p, desc->grid_owner);
+        check_grid_lds(p);
         p->tiles_per_side = p->K / p->tile;
         p->ntiles = p->tiles_per_side * p->tiles_per_side;
         RIOP_REQUIRE(p->ntiles <= 16384, RIOP_ENOTSUP, "too many gridding tiles; use a larger tile");
@@ -437,6 +437,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         p->tmp.alloc(cb * (size_t)p->K * p->n);
         p->grid.alloc(cb * (size_t)p->K * p->K);
         p->grid2.alloc(cb * (size_t)p->K * p->K);
+        p->halo.alloc(cb * (size_t)p->ntiles * grid_halo_cells(p->tile, p->J));
         p->vis.alloc(cb * (size_t)std::max<int64_t>(1, p->M));
         p->img.alloc(cb * N);
         size_t lls = 0;
@@ -446,7 +447,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         build_layout(p, uv, s);
         p->device_bytes = 0;
         for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->cell_start,
-                                &p->owner_order, &p->owner_count, &p->kcoef, &p->kcoef_owner, &p->deapod,
+                                &p->tile_order, &p->halo, &p->kcoef, &p->kcoef_compact, &p->deapod,
                                 &p->fft.twiddle, &p->tmp, &p->grid, &p->grid2, &p->vis, &p->img, &p->filters, &p->ll})
             p->device_bytes += (int64_t)b->bytes;
     });
@@ -477,7 +478,6 @@ riop_status riop_plan_info(const riop_plan *p, riop_info *info) {
         info->prec = p->prec;
         info->M = p->M;
         info->tile = p->tile;
-        info->grid_owner = p->owner;
         info->ntiles = p->ntiles;
         info->nunits = p->nunits;
         info->kernel_degree = p->kdeg;

@@ -99,11 +99,12 @@ static riop_plan *tuned_plan(const riop_desc &d0, const void *uv, int reps, hipS
     for (int i = 0; i < 4; ++i) {
         const int t = kTiles[i];
         const int K = 2 * d0.n;
-        if (K % t || (K / t) * (K / t) > 16384) continue;
+        if (K % t || t < d0.J || (K / t) * (K / t) > 16384) continue;
         riop_desc d = d0;
         d.tile = t;
         riop_plan *p = nullptr;
         riop_status st = riop_plan_create(&d, uv, s, &p);
+        if (st == RIOP_ENOTSUP) continue;  // e.g. the tile's gridding region does not fit in LDS
         if (st != RIOP_OK) throw Error{st, riop_last_error()};
         double m;
         try {

@@ -146,7 +146,6 @@ struct riop_plan {
 
     // Visibility layout (plan order).
     int tile = 0, tiles_per_side = 0, ntiles = 0;
-    int owner = 0, nowner = 0;  // gridding owner tile side (divides tile) and count
     size_t lds_max = 65536;     // LDS bytes one workgroup may use on the plan's device
     riop::DevBuf perm;        // int32[M]
     riop::DevBuf cell;        // uint32[M]: a0 | b0 << 16
@@ -154,8 +153,8 @@ struct riop_plan {
     riop::DevBuf tile_start;  // int32[ntiles + 1]
     riop::DevBuf units;       // WorkUnit[nunits] (degridding)
     riop::DevBuf cell_start;  // int32[K^2 + 1]: plan-order start of each cell key
-    riop::DevBuf owner_order; // int32[nowner]: gridding owner tiles, heaviest first
-    riop::DevBuf owner_count; // int32[nowner]: visibilities whose windows reach each owner tile
+    riop::DevBuf tile_order;  // int32[ntiles]: tiles, heaviest first (gridding)
+    riop::DevBuf halo;        // per tile: region cells outside the tile (gridding)
     int nunits = 0;
     int max_unit = 0;
 
@@ -166,7 +165,7 @@ struct riop_plan {
     double kfit_err = 0;
     riop::DevBuf kcoef;          // R[J/2][2][kMaxPoly]
     std::vector<double> kcoef_host;  // same table on the host, double
-    riop::DevBuf kcoef_owner;    // R[J/2][2][D/2 + 1] compact copy
+    riop::DevBuf kcoef_compact;  // R[J/2][2][D/2 + 1] compact copy
     riop::DevBuf deapod;         // R[n]: d(p - n/2)
 
     // FFT.
@@ -202,11 +201,10 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
 template <typename R>
 void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid = nullptr);
 // out_grid = G^T G in_grid (fused degrid + grid, the Gram part of Phi^dagger Phi).
-// Row stride (doubles) of the owner tile planes in LDS: 4 elements of padding
-// shift consecutive rows by 8 banks.
-inline int owner_stride(int O) { return O + 4; }
-// Picks the gridding owner tile side (0 = library choice).
-void choose_owner(riop_plan *p, int want_owner);
+// Throws RIOP_ENOTSUP if the plan's gridding tile needs more LDS than the device has.
+void check_grid_lds(riop_plan *p);
+// Complex cells of one tile's gridding halo slot.
+inline int grid_halo_cells(int T, int J) { return T * (J - 1) + (J - 1) * (T + J - 1); }
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
 template <typename R>
 void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st);

@@ -14,15 +14,17 @@
 // Neighbouring threads hold neighbouring cells, which keeps LDS bank conflicts
 // low.
 //
-// Gridding (G^T), owner computes: one workgroup per output tile.  It walks the
-// visibilities whose windows reach the tile (its own tile and the last J - 1
-// rows / columns of the three neighbours above and to the left, found through
-// cell_start), stages their weights in LDS, and each wavefront adds runs of
-// same-cell visibilities, one lane per window cell, into its private copy of
-// the tile with plain read-modify-write (no atomics: floating-point LDS
-// atomics are slow on this GPU).  The private copies are summed in a fixed
-// order and the tile is written once with plain stores: no zeroing, no global
-// atomics, and a reproducible result.
+// Gridding (G^T): one workgroup per sort tile.  Its visibilities are one
+// contiguous plan-order range and their windows reach only the tile and the
+// first J - 1 rows / columns of its neighbours below and to the right.  The
+// workgroup accumulates them into that (T + J - 1)-sided region, held in
+// double precision in LDS (runs of visibilities that share a window row and an
+// 8-aligned column block are summed in registers, on the matrix cores where
+// possible, and closed with LDS double atomic adds: floating-point LDS
+// atomics in single precision are slow on this GPU), then stores its own
+// cells to the grid and the rest to a halo slot; a second kernel adds each
+// tile's three incoming halos.  No zeroing of the grid, no global atomics,
+// and every visibility is read once.
 //
 // Kernel weights: for tap j the weight phi(rho + J/2 - 1 - j) is a polynomial
 // in s = 2 rho - 1 fitted at plan time; phi is even, so taps j and J-1-j share
@@ -312,81 +314,95 @@ __global__ void __launch_bounds__(kDegridThreads) degrid_kernel(GridArgs<R> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Gridding, owner computes.
-
-
-template <typename R> struct OwnerArgs {
-    C<R> *grid;               // output grid: every owned cell is written
-    const uint32_t *cell;     // plan order: a0 | b0 << 16
-    const R *frac;            // plan order: rho_u, rho_v
-    const int *perm;          // plan order -> caller order
-    const int *cell_start;    // K^2 + 1 plan-order offsets of the cell keys
-    const int *order;         // owner tiles, heaviest first
-    const int *count;         // visibilities whose windows reach each owner tile
-    const C<R> *vin;          // values to grid
-    const R *__restrict__ kc; // kernel coefficients [pair][even/odd][D/2 + 1]
-    int K, T, tps;            // grid side, sort tile side, sort tiles per side
-    int O, OS, ops;           // owner tile side (divides T), LDS row stride, owner tiles per side
-};
+// Gridding: one workgroup per sort tile.
 
 // Single-precision windows up to 8 wide are accumulated with matrix
 // instructions (v_mfma_f32_16x16x4_f32), the others with vector FMAs.
-template <typename R> __host__ __device__ constexpr bool owner_mfma(int J) { return sizeof(R) == 4 && J <= 8; }
+template <typename R> __host__ __device__ constexpr bool grid_mfma(int J) { return sizeof(R) == 4 && J <= 8; }
 
 // Row length of a wavefront's tap-major staging arrays.  Vector path: odd,
 // so the eight-address broadcast reads fall in distinct banks.  Matrix path:
 // 4 mod 32, so the operand reads (16 rows x 4 entries per instruction) hit 64
 // distinct banks.  Either way the staging stores (consecutive lanes) are
 // conflict-free.
-template <typename R> __host__ __device__ constexpr int slice_row(int J) { return owner_mfma<R>(J) ? 68 : 65; }
+template <typename R> __host__ __device__ constexpr int slice_row(int J) { return grid_mfma<R>(J) ? 68 : 65; }
 
 // LDS bytes of one wavefront's staging area.
-template <typename R> __host__ __device__ constexpr int owner_stage_bytes(int J) {
-    return ((int)sizeof(C<R>) * (owner_mfma<R>(J) ? 8 : J) + (int)sizeof(R) * 8 * ((J + 7) / 8 + 1)) * slice_row<R>(J);
+template <typename R> __host__ __device__ constexpr int grid_stage_bytes(int J) {
+    return ((int)sizeof(C<R>) * (grid_mfma<R>(J) ? 8 : J) + (int)sizeof(R) * 8 * ((J + 7) / 8 + 1)) * slice_row<R>(J);
 }
 
-// Wavefronts per owner workgroup: of 6, 4 and 2, the count that keeps the
-// most wavefronts resident per CU (160 KB of LDS, 32 x 32 owner tile),
-// preferring more wavefronts per tile on ties (shorter heavy tiles).
-template <typename R> __host__ __device__ constexpr int owner_waves(int J) {
-    const int tile = 2 * 8 * 32 * 36 + 2048;
-    const int st = owner_stage_bytes<R>(J);
+// Region of a T x T tile: the cells its visibilities' windows reach, rows
+// 0 .. T + J - 2 and columns 0 .. T + 8 NB - 1 (the run blocks are 8 NB + 8
+// wide and start at a multiple of 8 below T), held as two double planes.
+__host__ __device__ constexpr int region_rows(int T, int J) { return T + J - 1; }
+__host__ __device__ constexpr int region_stride(int T, int J) { return T + 8 * ((J + 7) / 8); }
+
+// Wavefronts per workgroup: of 6, 4 and 2, the count that keeps the most
+// wavefronts resident per CU (160 KB of LDS, 32 x 32 tile), preferring more
+// wavefronts per tile on ties (shorter heavy tiles).
+template <typename R> __host__ __device__ constexpr int grid_waves(int J) {
+    const int tile = 2 * 8 * region_rows(32, J) * region_stride(32, J) + 1024;
+    const int st = grid_stage_bytes<R>(J);
     const int w6 = 6 * (163840 / (6 * st + tile)), w4 = 4 * (163840 / (4 * st + tile)), w2 = 2 * (163840 / (2 * st + tile));
     return (w6 >= w4 && w6 >= w2 && w6 > 0) ? 6 : (w4 >= w2 && w4 > 0) ? 4 : 2;
 }
 
-template <typename R> static size_t owner_lds(int O, int OS, int J, int waves) {
-    const int NS = 2 * (O + J - 1);
-    return sizeof(double) * 2 * (size_t)O * OS + (size_t)owner_stage_bytes<R>(J) * waves +
-           sizeof(R) * (size_t)J * (KDeg<R>::D / 2 + 1) + sizeof(int) * (2 * (size_t)NS + 1);
+template <typename R> static size_t grid_lds(int T, int J, int waves) {
+    return sizeof(double) * 2 * (size_t)region_rows(T, J) * region_stride(T, J) +
+           (size_t)grid_stage_bytes<R>(J) * waves + sizeof(R) * (size_t)J * (KDeg<R>::D / 2 + 1);
 }
 
-// One workgroup per O x O owner tile; its wavefronts split the visibilities
-// whose windows reach the tile (contiguous in plan order per segment) into
-// contiguous shares and work independently, 64 visibilities (a slice) at a
-// time.
+// Halo of a tile: the region cells outside it, which belong to the tiles to
+// the right (right strip, T x (J-1)), below and below-right (bottom strip,
+// (J-1) x (T+J-1)).
+__host__ __device__ constexpr int halo_cells(int T, int J) { return T * (J - 1) + (J - 1) * (T + J - 1); }
+
+template <typename R> struct TileArgs {
+    C<R> *grid;               // own T x T cells of every tile
+    C<R> *halo;               // halo_cells(T, J) per tile
+    const uint32_t *cell;     // plan order: a0 | b0 << 16
+    const R *frac;            // plan order: rho_u, rho_v
+    const int *perm;          // plan order -> caller order
+    const int *tile_start;    // ntiles + 1 plan-order offsets
+    const int *order;         // tiles, heaviest first
+    const C<R> *vin;          // values to grid
+    const R *__restrict__ kc; // kernel coefficients [pair][even/odd][D/2 + 1]
+    int K, T, tps;            // grid side, tile side, tiles per side
+};
+
+// A tile's visibilities are one contiguous plan-order range; its wavefronts
+// take contiguous shares of it and work independently, 64 visibilities (a
+// slice) at a time.
 //
 // Staging: lane t of the wavefront takes visibility t of the slice and writes
 // its J row weights times the value, and its J column weights shifted by the
 // window's column offset inside an 8-aligned column block (zeros around them),
 // to the wavefront's own LDS area.
 //
-// Accumulation: the wavefront walks the slice one visibility per step; lane
-// (i, j) holds rows i + 8p of the window and columns j + 8q of the 8 (NB + 1)
-// wide column range that starts at the block.  In plan order, visibilities of
-// one window row and one column block are consecutive, so such a run is
-// summed in registers and added to the workgroup's tile only where it ends
-// (a bit mask built by one ballot per slice), with LDS double-precision atomic
-// adds: the tile is held in double for both precisions (on this GPU the double
-// LDS atomic is several times faster than the single one).  No workgroup
-// barrier inside the loop: a wavefront reads only what it staged itself.
-template <typename R, int J, bool USER>
-__global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R> a) {
-    constexpr int kOwnWaves = owner_waves<R>(J), kOwnThreads = 64 * kOwnWaves;
-    constexpr int NB = (J + 7) / 8;  // row slots per lane
+// Accumulation: the wavefront walks the slice one visibility per step.  In
+// plan order, visibilities of one window row and one column block are
+// consecutive, so such a run is summed in registers and added to the region
+// only where it ends (a bit mask built by one ballot per slice), with LDS
+// double-precision atomic adds: the region is held in double for both
+// precisions (on this GPU the double LDS atomic is several times faster than
+// the single one).  Matrix path: each group of 4 staged visibilities is one
+// 16 x 16 x 4 product, A = window rows (real, imaginary) x entries, B =
+// entries x column slots.  Vector path: lane (i, j) holds window rows i + 8p
+// and column slots j + 8q.  No workgroup barrier inside the loop: a wavefront
+// reads only what it staged itself.
+//
+// The workgroup finally stores its own T x T cells to the grid and the rest
+// of the region to its halo slot; grid_merge adds the halos of the three
+// neighbours a tile receives from.
+// WAVES: grid_waves<R>(J), or 2 for tiles whose region leaves too little LDS.
+template <typename R, int J, bool USER, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
+    constexpr int kWaves = WAVES, kThreads = 64 * kWaves;
+    constexpr int NB = (J + 7) / 8;  // row slots per lane (vector path)
     constexpr int QB = NB + 1;       // column slots per lane
     constexpr int NC = 8 * QB;       // staged column-weight rows
-    constexpr bool MF = owner_mfma<R>(J);
+    constexpr bool MF = grid_mfma<R>(J);
     constexpr int JR = MF ? 8 : J;   // staged row-weight rows
     constexpr int SR = slice_row<R>(J);
     constexpr int BATCH = sizeof(R) == 8 ? (J > 12 ? 2 : 4) : (J > 8 ? 4 : 8);
@@ -396,72 +412,23 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
     constexpr bool kUnroll = !(sizeof(R) == 8 && J > 12);
     constexpr int KS = KDeg<R>::D / 2 + 1;
     extern __shared__ unsigned char smem_raw[];
-    const int T = a.T, K = a.K, tps = a.tps, O = a.O, OS = a.OS, PS = O * OS;
-    const int NR = O + J - 1, NS = 2 * NR;
-    double *tre = reinterpret_cast<double *>(smem_raw);                   // [O][OS] real parts
-    double *tim = tre + PS;                                               // [O][OS] imaginary parts
+    const int T = a.T, K = a.K, tps = a.tps;
+    const int RR = region_rows(T, J), RS = region_stride(T, J), PS = RR * RS;
+    double *tre = reinterpret_cast<double *>(smem_raw);                   // [RR][RS] real parts
+    double *tim = tre + PS;                                               // [RR][RS] imaginary parts
     C<R> *wuv_all = reinterpret_cast<C<R> *>(tim + PS);                   // [waves][JR][SR]: wu_i * value
-    R *wv_all = reinterpret_cast<R *>(wuv_all + (size_t)kOwnWaves * JR * SR);  // [waves][NC][SR]
-    R *kcl = wv_all + (size_t)kOwnWaves * NC * SR;                        // [J/2][2][KS]
-    int *segbeg = reinterpret_cast<int *>(kcl + (J / 2) * 2 * KS);         // [NS]
-    int *segoff = segbeg + NS;                                            // [NS + 1]
+    R *wv_all = reinterpret_cast<R *>(wuv_all + (size_t)kWaves * JR * SR);  // [waves][NC][SR]
+    R *kcl = wv_all + (size_t)kWaves * NC * SR;                           // [J/2][2][KS]
     const int tid = threadIdx.x;
     if constexpr (!kScalarCoef)
-        for (int i = tid; i < (J / 2) * 2 * KS; i += kOwnThreads) kcl[i] = a.kc[i];
+        for (int i = tid; i < (J / 2) * 2 * KS; i += kThreads) kcl[i] = a.kc[i];
 
-    const int ot = a.order[blockIdx.x];
-    const int oa = (ot / a.ops) * O, ob = (ot % a.ops) * O;
-    if (a.count[ot] == 0) {  // no window reaches the tile
-        for (int c = tid; c < O * O; c += kOwnThreads) {
-            const int r = c / O, col = c - r * O;
-            a.grid[(int64_t)(oa + r) * K + ob + col] = mk<R>(0, 0);
-        }
-        return;
-    }
-    // Extended region: base-cell rows oa - (J-1) .. oa + O - 1 and columns
-    // ob - (J-1) .. ob + O - 1 (mod K).  Each row is split at the sort-tile
-    // boundary into at most two key-contiguous pieces (O divides T, J <= T).
-    const int cs = (ob - (J - 1) + K) % K;
-    const int tc0 = cs / T, lc0 = cs % T;
-    const int len0 = min(NR, T - lc0), len1 = NR - len0, tc1 = (tc0 + 1) % tps;
-    for (int sgi = tid; sgi < NS; sgi += kOwnThreads) {
-        const int r = sgi >> 1, piece = sgi & 1;
-        const int ar = (oa - (J - 1) + r + K) % K;
-        const int tr = ar / T, lr = ar % T;
-        const int64_t k0 = (int64_t)(tr * tps + (piece ? tc1 : tc0)) * T * T + lr * T + (piece ? 0 : lc0);
-        const int b = a.cell_start[k0];
-        segbeg[sgi] = b;
-        segoff[sgi + 1] = a.cell_start[k0 + (piece ? len1 : len0)] - b;
-    }
-    for (int c = tid; c < 2 * PS; c += kOwnThreads) tre[c] = 0.0;
+    const int t = a.order[blockIdx.x];
+    const int v0 = a.tile_start[t], total = a.tile_start[t + 1] - v0;
+    const int ta = (t / tps) * T, tb = (t % tps) * T;
+    for (int c = tid; c < 2 * PS; c += kThreads) tre[c] = 0.0;
     __syncthreads();
-    if (tid < 64) {
-        // Scan of the segment lengths by the first wavefront: lane l holds
-        // segments 4l .. 4l + 3 (NS <= 2 * (64 + 15) < 256).
-        int len[4], x = 0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int k = 4 * tid + m + 1;
-            len[m] = k <= NS ? segoff[k] : 0;
-            x += len[m];
-        }
-        const int own = x;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(x, d);
-            if (tid >= d) x += y;
-        }
-        int run = x - own;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int k = 4 * tid + m + 1;
-            run += len[m];
-            if (k <= NS) segoff[k] = run;
-        }
-        if (tid == 0) segoff[0] = 0;
-    }
-    __syncthreads();
-    const int total = segoff[NS];
+
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, li = lane >> 3, lj = lane & 7;
     C<R> *wuv = wuv_all + wave * JR * SR;
@@ -472,40 +439,24 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
 
     // This wavefront's slices.
     const int nsl = (total + 63) >> 6;
-    const int s_begin = (wave * nsl) / kOwnWaves, s_end = ((wave + 1) * nsl) / kOwnWaves;
+    const int s_begin = (wave * nsl) / kWaves, s_end = ((wave + 1) * nsl) / kWaves;
 
-    // The visibility this lane stages next: its segment, the slice position
-    // where the segment ends, its plan index, cell, offsets and value.  A
-    // lane's position advances by 64 per slice, so the segment search runs
-    // only when the lane leaves its segment.
-    int seg = 0, bnd = 0, v = 0;
+    // The visibility this lane stages next: cell, offsets and value.
     uint32_t cv = 0;
     R fu = 0, fv = 0;
     C<R> val = mk<R>(0, 0);
-    auto locate = [&](int f, int lo) {
-        int hi = NS;  // segoff[lo] <= f < segoff[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (segoff[mid] <= f) lo = mid; else hi = mid;
-        }
-        seg = lo;
-        v = segbeg[lo] + (f - segoff[lo]);
-        bnd = segoff[lo + 1];
-    };
-    auto load = [&]() {
-        cv = a.cell[v];
-        fu = a.frac[2 * (int64_t)v];
-        fv = a.frac[2 * (int64_t)v + 1];
-        val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
-    };
-    if (s_begin < s_end) {
-        const int f = s_begin * 64 + lane;
+    auto load = [&](int f) {
         if (f < total) {
-            locate(f, 0);
-            load();
+            const int v = v0 + f;
+            cv = a.cell[v];
+            fu = a.frac[2 * (int64_t)v];
+            fv = a.frac[2 * (int64_t)v + 1];
+            val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
         }
-    }
+    };
+    if (s_begin < s_end) load(s_begin * 64 + lane);
 
+    // Vector path state.
     int ic[NB], jc[QB];
 #pragma unroll
     for (int p = 0; p < NB; ++p) ic[p] = min(li + 8 * p, J - 1) * SR;
@@ -516,41 +467,36 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
     for (int p = 0; p < NB; ++p)
 #pragma unroll
         for (int q = 0; q < QB; ++q) acc[p][q] = mk<R>(0, 0);
-    // Closing a run adds its sums to the tile cells it covers inside the owner tile.
+    // Closing a run adds its sums to the region cells its window block covers.
     auto close_run = [&](int pos) {
-        const int la = (pos >> 8) - J, cb = ((pos & 255) << 3) - J;
+        const int la = pos >> 8, cb = (pos & 255) << 3;
 #pragma unroll
         for (int p = 0; p < NB; ++p)
 #pragma unroll
             for (int q = 0; q < QB; ++q) {
                 const int i = li + 8 * p;
-                const int ra = la + i, rb = cb + lj + 8 * q;
-                if (i < J && (unsigned)ra < (unsigned)O && (unsigned)rb < (unsigned)O) {
-                    const int c = ra * OS + rb;
+                if (i < J) {
+                    const int c = (la + i) * RS + cb + lj + 8 * q;
                     __hip_atomic_fetch_add(tre + c, (double)acc[p][q].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     __hip_atomic_fetch_add(tim + c, (double)acc[p][q].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 acc[p][q] = mk<R>(0, 0);
             }
     };
-    // Matrix path: one 16 x 16 x 4 product per group of 4 staged entries,
-    // A[i][k] = component i % 2 of window row i / 2 of entry k (lane i + 16k),
-    // B[k][j] = column slot j of entry k (lane j + 16k); lane l then holds
-    // D[4 (l / 16) + r][l % 16], i.e. window rows 2 (l / 16) and 2 (l / 16) + 1
-    // (real, imaginary) of column slot l % 16.
+    // Matrix path state: lane l holds D[4 (l / 16) + r][l % 16], i.e. window
+    // rows 2 (l / 16) and 2 (l / 16) + 1 (real, imaginary) of column slot l % 16.
     typedef float mf4 __attribute__((ext_vector_type(4)));
     mf4 dacc = {0.f, 0.f, 0.f, 0.f};
     const int mk_ = lane >> 4, mi = lane & 15;
     const int abase = 2 * ((mi >> 1) * SR + mk_) + (mi & 1);  // float index into wuv
     const int bbase = mi * SR + mk_;                          // index into wv
     auto close_run_mf = [&](int pos) {
-        const int la = (pos >> 8) - J, cb = ((pos & 255) << 3) - J;
-        const int rb = cb + mi;
+        const int la = pos >> 8, cb = (pos & 255) << 3;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int i = 2 * mk_ + h, ra = la + i;
-            if (i < J && (unsigned)ra < (unsigned)O && (unsigned)rb < (unsigned)O) {
-                const int c = ra * OS + rb;
+            const int i = 2 * mk_ + h;
+            if (i < J) {
+                const int c = (la + i) * RS + cb + mi;
                 __hip_atomic_fetch_add(tre + c, (double)dacc[2 * h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __hip_atomic_fetch_add(tim + c, (double)dacc[2 * h + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
@@ -565,11 +511,9 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
         // Staging.  Lanes past the end stage zero values, so the
         // accumulation below runs over all 64 entries without bound tests.
         if (!live) val = mk<R>(0, 0);
-        const int r = seg >> 1, piece = seg & 1;
-        const int la = r - (J - 1);
-        const int cb8 = (int)((cv >> 16) & (uint32_t)(T - 1)) + (piece ? len0 : -lc0) + 1;  // lb + J, in [1, O + J]
-        const int pos = live ? ((la + J) << 8) | (cb8 >> 3) : -1;
-        const int db = cb8 & 7;
+        const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;  // in [0, T)
+        const int pos = live ? (la << 8) | (lb >> 3) : -1;
+        const int db = lb & 7;
         {
             R wu_[J], wv_[J];
             if constexpr (kScalarCoef) {
@@ -597,14 +541,7 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
         const uint64_t starts = __ballot(live && pos != prev);
         __builtin_amdgcn_wave_barrier();
         // The next slice's visibility: global loads in flight during the accumulation.
-        if (sl + 1 < s_end) {
-            const int f = base + 64 + lane;
-            if (f < total) {
-                if (f >= bnd) locate(f, seg + 1);
-                else v += 64;
-                load();
-            }
-        }
+        if (sl + 1 < s_end) load(base + 64 + lane);
 
         if constexpr (MF) {
             // Groups of 4 entries; a group holding run starts is split into
@@ -636,29 +573,29 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
                 }
             }
         } else {
-        // Accumulation: one staged visibility per step; unrolled over the
-            // slice (constant bit tests, immediate offsets) where registers allow,
-            // with the reads of the next batch issued before the current batch is
-            // used.
+            // One staged visibility per step; unrolled over the slice
+            // (constant bit tests, immediate offsets) where registers allow,
+            // with the reads of the next batch issued before the current
+            // batch is used.
             auto fetch_batch = [&](int kb, C<R> (&us)[BATCH][NB], R (&ws)[BATCH][QB]) {
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < BATCH; ++k) {
-    #pragma unroll
+#pragma unroll
                     for (int p = 0; p < NB; ++p) us[k][p] = wuv[ic[p] + kb + k];
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < QB; ++q) ws[k][q] = wv[jc[q] + kb + k];
                 }
             };
             auto use_batch = [&](int kb, const C<R> (&us)[BATCH][NB], const R (&ws)[BATCH][QB]) {
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < BATCH; ++k) {
                     if (__builtin_expect((starts >> (kb + k)) & 1, 0)) {
                         if (cur >= 0) close_run(cur);
                         cur = __builtin_amdgcn_readlane(pos, kb + k);
                     }
-    #pragma unroll
+#pragma unroll
                     for (int p = 0; p < NB; ++p)
-    #pragma unroll
+#pragma unroll
                         for (int q = 0; q < QB; ++q) {
                             acc[p][q].x += us[k][p].x * ws[k][q];
                             acc[p][q].y += us[k][p].y * ws[k][q];
@@ -669,7 +606,7 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
                 C<R> u0[BATCH][NB], u1[BATCH][NB];
                 R w0[BATCH][QB], w1[BATCH][QB];
                 fetch_batch(0, u0, w0);
-    #pragma unroll
+#pragma unroll
                 for (int kb = 0; kb < 64; kb += 2 * BATCH) {
                     fetch_batch(kb + BATCH, u1, w1);
                     use_batch(kb, u0, w0);
@@ -677,7 +614,7 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
                     use_batch(kb + BATCH, u1, w1);
                 }
             } else {
-    #pragma unroll 1
+#pragma unroll 1
                 for (int kb = 0; kb < 64; kb += BATCH) {
                     C<R> u0[BATCH][NB];
                     R w0[BATCH][QB];
@@ -694,11 +631,51 @@ __global__ void __launch_bounds__(64 * owner_waves<R>(J)) grid_owner(OwnerArgs<R
         else close_run(cur);
     }
     __syncthreads();
-    // Store the tile.
-    for (int c = tid; c < O * O; c += kOwnThreads) {
-        const int r = c / O, col = c - r * O;
-        a.grid[(int64_t)(oa + r) * K + ob + col] = mk<R>((R)tre[r * OS + col], (R)tim[r * OS + col]);
+    // Own cells to the grid, the rest of the region to the halo slot.
+    for (int c = tid; c < T * T; c += kThreads) {
+        const int r = c / T, col = c - r * T;
+        a.grid[(int64_t)(ta + r) * K + tb + col] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
     }
+    C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
+    for (int c = tid; c < T * (J - 1); c += kThreads) {  // right strip
+        const int r = c / (J - 1), col = T + c - r * (J - 1);
+        halo[c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    }
+    for (int c = tid; c < (J - 1) * (T + J - 1); c += kThreads) {  // bottom strip with the corner
+        const int r = T + c / (T + J - 1), col = c % (T + J - 1);
+        halo[T * (J - 1) + c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    }
+}
+
+// Adds to each tile's first J-1 rows and columns what the tiles above, to
+// the left and above-left left in their halo slots (periodic in the tile
+// grid), in that fixed order.  One thread per border cell.
+template <typename R>
+__global__ void grid_merge(C<R> *grid, const C<R> *halo, int K, int T, int J, int tps) {
+    const int per = (J - 1) * (2 * T - J + 1);  // border cells per tile
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)tps * tps * per) return;
+    const int d = (int)(g / per), e = (int)(g % per);
+    int i, j;
+    if (e < (J - 1) * T) {
+        i = e / T;
+        j = e % T;
+    } else {
+        const int e2 = e - (J - 1) * T;
+        i = J - 1 + e2 / (J - 1);
+        j = e2 % (J - 1);
+    }
+    const int dr = d / tps, dc = d % tps;
+    const int up = ((dr + tps - 1) % tps) * tps + dc;
+    const int left = dr * tps + (dc + tps - 1) % tps;
+    const int ul = ((dr + tps - 1) % tps) * tps + (dc + tps - 1) % tps;
+    const int HC = halo_cells(T, J);
+    const int64_t cell = (int64_t)(dr * T + i) * K + dc * T + j;
+    C<R> v = grid[cell];
+    if (i < J - 1) v = cadd<R>(v, halo[(int64_t)up * HC + T * (J - 1) + i * (T + J - 1) + j]);
+    if (j < J - 1) v = cadd<R>(v, halo[(int64_t)left * HC + i * (J - 1) + j]);
+    if (i < J - 1 && j < J - 1) v = cadd<R>(v, halo[(int64_t)ul * HC + T * (J - 1) + i * (T + J - 1) + T + j]);
+    grid[cell] = v;
 }
 
 template <typename R> __global__ void fill_zero_kernel(C<R> *buf, int64_t n) {
@@ -795,34 +772,14 @@ template <typename R> static void build_layout_t(riop_plan *p, const void *uv, h
         RIOP_HIP(hipMemcpyAsync(p->units.ptr, units.data(), sizeof(WorkUnit) * units.size(),
                                 hipMemcpyHostToDevice, st));
 
-    // Gridding owner tiles, heaviest first: the work of an owner tile is the
-    // number of visibilities whose first window cell lies in its extended region.
-    const int O = p->owner, ops = K / O, nowner = ops * ops, NR = O + J - 1;
-    std::vector<std::pair<int64_t, int>> work(nowner);
-    for (int ot = 0; ot < nowner; ++ot) {
-        const int oa = (ot / ops) * O, ob = (ot % ops) * O;
-        const int cs0 = (ob - (J - 1) + K) % K, tc0 = cs0 / T, lc0 = cs0 % T;
-        const int len0 = std::min(NR, T - lc0), len1 = NR - len0, tc1 = (tc0 + 1) % tps;
-        int64_t w = 0;
-        for (int r = 0; r < NR; ++r) {
-            const int ar = (oa - (J - 1) + r + K) % K, tr = ar / T, lr = ar % T;
-            const int64_t k0 = (int64_t)(tr * tps + tc0) * T * T + lr * T + lc0;
-            const int64_t k1 = (int64_t)(tr * tps + tc1) * T * T + lr * T;
-            w += cs[k0 + len0] - cs[k0];
-            w += cs[k1 + len1] - cs[k1];
-        }
-        work[ot] = {w, ot};
-    }
-    std::vector<int> count(nowner);
-    for (int ot = 0; ot < nowner; ++ot) count[ot] = (int)work[ot].first;
+    // Gridding: sort tiles, heaviest first.
+    std::vector<std::pair<int, int>> work(ntiles);
+    for (int t = 0; t < ntiles; ++t) work[t] = {ts[t + 1] - ts[t], t};
     std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-    std::vector<int> order(nowner);
-    for (int t = 0; t < nowner; ++t) order[t] = work[t].second;
-    p->owner_count.alloc(sizeof(int) * nowner);
-    RIOP_HIP(hipMemcpyAsync(p->owner_count.ptr, count.data(), sizeof(int) * nowner, hipMemcpyHostToDevice, st));
-    p->nowner = nowner;
-    p->owner_order.alloc(sizeof(int) * nowner);
-    RIOP_HIP(hipMemcpyAsync(p->owner_order.ptr, order.data(), sizeof(int) * nowner, hipMemcpyHostToDevice, st));
+    std::vector<int> order(ntiles);
+    for (int t = 0; t < ntiles; ++t) order[t] = work[t].second;
+    p->tile_order.alloc(sizeof(int) * ntiles);
+    RIOP_HIP(hipMemcpyAsync(p->tile_order.ptr, order.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, st));
     RIOP_HIP(hipStreamSynchronize(st));
 }
 
@@ -882,62 +839,68 @@ template <typename R> void launch_degrid(riop_plan *p, void *y, int order_user, 
     launch_degrid_from<R>(p, p->grid.ptr, y, order_user, st);
 }
 
-void choose_owner(riop_plan *p, int want_owner) {
-    const bool f64 = p->prec == RIOP_F64;
-    const int O = want_owner ? want_owner : std::min(p->tile, 32);
-    RIOP_REQUIRE(O >= 8 && O <= p->tile && (O & (O - 1)) == 0, RIOP_EINVAL,
-                 "grid_owner must be a power of two in [8, tile]");
-    const size_t lds = f64 ? owner_lds<double>(O, owner_stride(O), p->J, owner_waves<double>(p->J))
-                           : owner_lds<float>(O, owner_stride(O), p->J, owner_waves<float>(p->J));
-    RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding owner tile too large for LDS");
-    p->owner = O;
+void check_grid_lds(riop_plan *p) {
+    const size_t lds = p->prec == RIOP_F64 ? grid_lds<double>(p->tile, p->J, 2) : grid_lds<float>(p->tile, p->J, 2);
+    RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding tile too large for LDS; use a smaller tile");
 }
 
 template <typename R>
-static void launch_owner(riop_plan *p, const void *vals, int order_user, void *out_grid, hipStream_t st) {
-    OwnerArgs<R> a{};
+static void launch_tiles(riop_plan *p, const void *vals, int order_user, void *out_grid, hipStream_t st) {
+    TileArgs<R> a{};
     a.grid = static_cast<C<R> *>(out_grid);
+    a.halo = p->halo.as<C<R>>();
     a.cell = p->cell.as<uint32_t>();
     a.frac = p->frac.as<R>();
     a.perm = p->perm.as<int>();
-    a.cell_start = p->cell_start.as<int>();
-    a.order = p->owner_order.as<int>();
-    a.count = p->owner_count.as<int>();
+    a.tile_start = p->tile_start.as<int>();
+    a.order = p->tile_order.as<int>();
     a.vin = static_cast<const C<R> *>(vals);
-    a.kc = p->kcoef_owner.as<R>();
+    a.kc = p->kcoef_compact.as<R>();
     a.K = p->K;
     a.T = p->tile;
     a.tps = p->tiles_per_side;
-    a.O = p->owner;
-    a.OS = owner_stride(p->owner);
-    a.ops = p->K / p->owner;
-    const int waves = owner_waves<R>(p->J);
-    const size_t lds = owner_lds<R>(a.O, a.OS, p->J, waves);
-    RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding owner tile too large for LDS");
+    int waves = grid_waves<R>(p->J);
+    if (grid_lds<R>(p->tile, p->J, waves) > p->lds_max) waves = 2;
+    const size_t lds = grid_lds<R>(p->tile, p->J, waves);
+    RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding tile too large for LDS");
     TimedScope ts(p, KK_GRID, st);
+    const dim3 g(p->ntiles);
     switch (p->J) {
-#define GK(JJ)                                                                                                    \
-    case JJ:                                                                                                      \
-        if (order_user)                                                                                           \
-            hipLaunchKernelGGL((grid_owner<R, JJ, true>), dim3(p->nowner), dim3(64 * waves), lds, st, a);       \
-        else                                                                                                      \
-            hipLaunchKernelGGL((grid_owner<R, JJ, false>), dim3(p->nowner), dim3(64 * waves), lds, st, a);      \
-        break;
+#define GK(JJ)                                                                                            \
+    case JJ: {                                                                                            \
+        constexpr int WD = grid_waves<R>(JJ);                                                             \
+        if (waves == WD) {                                                                                \
+            if (order_user) hipLaunchKernelGGL((grid_tile<R, JJ, true, WD>), g, dim3(64 * WD), lds, st, a);   \
+            else hipLaunchKernelGGL((grid_tile<R, JJ, false, WD>), g, dim3(64 * WD), lds, st, a);             \
+        } else {                                                                                          \
+            if (order_user) hipLaunchKernelGGL((grid_tile<R, JJ, true, 2>), g, dim3(128), lds, st, a);         \
+            else hipLaunchKernelGGL((grid_tile<R, JJ, false, 2>), g, dim3(128), lds, st, a);                   \
+        }                                                                                                 \
+        break;                                                                                            \
+    }
         RIOP_J_CASES(GK)
 #undef GK
         default: throw Error{RIOP_ENOTSUP, "unsupported kernel width"};
     }
     RIOP_HIP(hipGetLastError());
+    const int64_t cells = (int64_t)p->ntiles * (p->J - 1) * (2 * p->tile - p->J + 1);
+    if (cells > 0) {
+        const int threads = 256;
+        hipLaunchKernelGGL(grid_merge<R>, dim3((unsigned)((cells + threads - 1) / threads)), dim3(threads), 0, st,
+                           static_cast<C<R> *>(out_grid), (const C<R> *)p->halo.as<C<R>>(), p->K, p->tile, p->J,
+                           p->tiles_per_side);
+        RIOP_HIP(hipGetLastError());
+    }
 }
 
 template <typename R> void launch_grid(riop_plan *p, const void *y, int order_user, hipStream_t st) {
-    launch_owner<R>(p, y, order_user, p->grid.ptr, st);
+    launch_tiles<R>(p, y, order_user, p->grid.ptr, st);
 }
 
-// out_grid = G^T G in_grid: degridding into plan-order scratch, then owner gridding.
+// out_grid = G^T G in_grid: degridding into plan-order scratch, then gridding.
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st) {
     launch_degrid_from<R>(p, in_grid, p->vis.ptr, 0, st);
-    launch_owner<R>(p, p->vis.ptr, 0, out_grid, st);
+    launch_tiles<R>(p, p->vis.ptr, 0, out_grid, st);
 }
 
 template void launch_gram<float>(riop_plan *, const void *, void *, hipStream_t);

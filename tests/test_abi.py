@@ -47,8 +47,8 @@ def test_struct_layouts_match_header():
 int main(void) {
   printf("riop_desc %zu\nriop_info %zu\nriop_sdmm_params %zu\nriop_sdmm_stats %zu\n",
          sizeof(riop_desc), sizeof(riop_info), sizeof(riop_sdmm_params), sizeof(riop_sdmm_stats));
-  P(riop_desc, M) P(riop_desc, tile) P(riop_desc, grid_owner) P(riop_desc, reserved)
-  P(riop_info, M) P(riop_info, kb_beta) P(riop_info, device_bytes) P(riop_info, grid_owner)
+  P(riop_desc, M) P(riop_desc, tile) P(riop_desc, reserved)
+  P(riop_info, M) P(riop_info, kb_beta) P(riop_info, device_bytes)
   P(riop_sdmm_params, gamma) P(riop_sdmm_params, weights) P(riop_sdmm_params, history)
   P(riop_sdmm_stats, gamma) P(riop_sdmm_stats, nu)
   return 0;

@@ -70,27 +70,6 @@ def test_wide_kernels(prec, J):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("owner", [8, 16, 32])
-def test_owner_sizes_agree(prec, owner):
-    """Every gridding owner tile side gives the oracle's result."""
-    n, M, J = 64, 9000, 8
-    device()
-    announce(f"owner {owner} {prec}")
-    uv, x, w = _inputs(n, M, prec, 13)
-    op = nufft.Operator(n, uv, J)
-    from paper_1307_4370_amd import Plan, RiopError
-    try:
-        plan = Plan(n, to_dev(uv, prec), J=J, levels=1, prec=prec, tile=32, grid_owner=owner)
-    except RiopError as e:
-        if e.status == -5:  # RIOP_ENOTSUP: more LDS than one workgroup may use on this device
-            pytest.skip(str(e))
-        raise
-    assert plan.info()["grid_owner"] == owner
-    assert rel(host(plan.phi_adj(to_dev(w, prec))), op.phi_adj(w)) <= TOL[prec]
-    assert rel(host(plan.apply_q(to_dev(x, prec))), op.phi_adj(op.phi(x)) + 2 * x) <= TOL[prec]
-
-
-@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("tile", [8, 16, 32, 64])
 def test_tile_shapes_agree(prec, tile):
     """Every gridding tile size gives the oracle's result (gridding races would show here)."""

@@ -38,6 +38,84 @@ sys.path.insert(0, ROOT)
 
 METRIC = "visibilities/s through Phi+Phi^dagger and SDMM iters/s at 1024^2, FP32 vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
+GRID_SOURCE = os.path.join(ROOT, "paper_1307_4370_amd", "csrc", "gridding.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_fp32_1024sq_M4194304_hbm_traffic.md")
+
+
+def source_hash(path=GRID_SOURCE):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per FP32 gridding launch from the committed counter summary, or None
+    when the summary is missing or was taken on a different gridding source."""
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = re.search(r"gridding source sha256/16: `([0-9a-f]+)`", text)
+    b = re.search(r"HBM bytes per gridding launch: `([0-9.e+]+)`", text)
+    if not h or not b or h.group(1) != source_hash():
+        return None
+    return float(b.group(1))
+
+
+def traffic_summary(fetch_dir, write_dir, probe_mib):
+    """Write the HBM-traffic summary of the FP32 gridding launch from two rocprofv3
+    --pmc runs (FETCH_SIZE, then WRITE_SIZE), each calibrated on a plain device copy
+    of probe_mib MiB (the largest __amd_rocclr_copyBuffer dispatch of the run)."""
+    import csv, glob, collections
+
+    def per_dispatch(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        vals = collections.defaultdict(float)
+        names = {}
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (f, r["Dispatch_Id"])
+                vals[key] += float(r["Counter_Value"])
+                names[key] = r["Kernel_Name"]
+        return [(names[k], v * 1024.0) for k, v in vals.items()]  # KiB -> bytes
+
+    probe = probe_mib * 2 ** 20
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = per_dispatch(d, counter)
+        copies = [v for n, v in rows if "copyBuffer" in n]
+        cal = probe / max(copies) if copies else 1.0
+        tile = [v for n, v in rows if "grid_tile<float, 8, false" in n]
+        merge = [v for n, v in rows if "grid_merge<float>" in n]
+        t = sum(tile) / len(tile) if tile else 0.0
+        m = sum(merge) / len(merge) if merge else 0.0
+        out[counter] = dict(cal=cal, tile=t * cal, merge=m * cal, n_tile=len(tile), n_merge=len(merge),
+                            probe_raw=max(copies) if copies else 0.0)
+    total = sum(out[c]["tile"] + out[c]["merge"] for c in out)
+    lines = ["# HBM traffic of the FP32 gridding launch, 1024^2, M = 4194304, J = 8 (grid_tile + grid_merge)\n",
+             "Commands (repository root on the MI355X host, one counter pass each):\n", "```",
+             "cd /tmp && export TMPDIR=/tmp",
+             f"timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o t -- "
+             f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --copy-probe {probe_mib}",
+             f"timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o t -- "
+             f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --copy-probe {probe_mib}",
+             f"python3 $REPO/bench.py --traffic-summary $REPO/gpurun_out/pmc_fetch $REPO/gpurun_out/pmc_write "
+             f"--copy-probe {probe_mib}", "```\n",
+             f"Calibration: a plain {probe_mib} MiB device copy; its counter reading is scaled to exactly "
+             f"{probe_mib} MiB read and written.\n",
+             "| counter | copy-probe reading (bytes) | factor | grid_tile per launch (bytes) | grid_merge per launch (bytes) | launches |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for c in out:
+        o = out[c]
+        lines.append(f"| {c} | {o['probe_raw']:.4g} | {o['cal']:.4f} | {o['tile']:.4g} | {o['merge']:.4g} | "
+                     f"{o['n_tile']}/{o['n_merge']} |")
+    lines += ["", f"HBM bytes per gridding launch: `{total:.6g}`", "",
+              f"Algorithmic bytes per launch (32N + 16M, FP32): {algorithmic_bytes('grid', 1024, 4194304, 8):.6g}", "",
+              f"gridding source sha256/16: `{source_hash()}`", ""]
+    open(TRAFFIC_FILE, "w").write("\n".join(lines))
+    print("\n".join(lines))
 
 
 def log(msg):
@@ -111,7 +189,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the run, copy this many MiB device to device (counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the gridding HBM-traffic summary from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.copy_probe or 512)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the visibilities would be sharded); run with --gpus 1",
@@ -196,8 +281,9 @@ def main():
     tot_ms, launches = kernels[dom]
     avg_s = tot_ms * 1e-3 / max(1, launches)
     ach = algorithmic_bytes(dom, n, M, cb) / avg_s / 1e9
+    traffic = recorded_traffic() if dom == "grid" else None
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_us": round(avg_s * 1e6, 2)}
     kern = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                 "avg_us": round(v[0] * 1e3 / v[1], 2) if v[1] else None,
@@ -237,6 +323,16 @@ def main():
                 "pair_visibilities_per_s": pair_rate(plan64, xd64, yb64, False, max(2, args.pairs // 4))}
         log(f"fp64: {fp64}")
         del plan64, yb64
+
+    if args.copy_probe:
+        nb = args.copy_probe * 2 ** 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB x 3")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

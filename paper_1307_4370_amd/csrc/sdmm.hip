@@ -22,7 +22,7 @@ constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
 
 // Partial-sum slots (each kRedBlocks doubles).
-enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, kSlots };
+enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, SLOT_F1, kSlots };
 // Scalar slots.
 enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, kScalars };
 
@@ -237,25 +237,23 @@ template <typename R> __global__ void add3(const C<R> *a, const C<R> *b, const C
     }
 }
 
+// First stage of f1 over the analysis blocks' partials: block b sums every
+// (kRedBlocks * kRedThreads)-th partial from its own offset into slot SLOT_F1.
+__global__ void f1_partials(const double *f1part, int f1_count, double *partials) {
+    double v = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < f1_count; i += kRedBlocks * kRedThreads) v += f1part[i];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partials[SLOT_F1 * kRedBlocks + blockIdx.x] = s;
+}
+
 // history[t] = {f1, zeta, nu, final CG rr} with t the device iteration
 // counter (so a captured graph can be replayed); f1_prev <- f1; t <- t + 1.
-__global__ void record_stats(const double *partials, double *scalars, double *hist, int cap, int rr_slot,
-                             const double *f1part, int f1_count) {
+__global__ void record_stats(const double *partials, double *scalars, double *hist, int cap, int rr_slot) {
     const double nu2 = slot_sum(partials, SLOT_NU);
     const double rr = slot_sum(partials, rr_slot);
-    // f1: the analysis blocks' partials, added in a fixed order.
-    __shared__ double red[kRedThreads];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < f1_count; i += kRedThreads) v += f1part[i];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
+    const double f1 = slot_sum(partials, SLOT_F1);
     if (threadIdx.x == 0) {
         const int t = (int)scalars[SC_ITER];
-        const double f1 = red[0];
         scalars[SC_F1ACC] = f1;
         const double prev = scalars[SC_F1PREV];
         const double zeta = prev == 0.0 ? INFINITY : fabs(f1 - prev) / fabs(prev);
@@ -445,8 +443,9 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         // i = 3 and the next right-hand side.
         VEC_LAUNCH(p, prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(), w.x1.as<C<R>>(),
                    w.tmpN.as<C<R>>(), w.rhs.as<C<R>>(), N);
+        VEC_LAUNCH(p, f1_partials, RB(), RT(), 0, s, (const double *)w.f1part.as<double>(), w.f1_count, part);
         VEC_LAUNCH(p, record_stats, dim3(1), RT(), 0, s, (const double *)part, sc, w.history.as<double>(),
-                   w.hist_cap, rr_slot, (const double *)w.f1part.as<double>(), w.f1_count);
+                   w.hist_cap, rr_slot);
         RIOP_HIP(hipGetLastError());
     }
 }

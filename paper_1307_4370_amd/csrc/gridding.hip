@@ -371,9 +371,30 @@ template <typename R> struct TileArgs {
     int K, T, tps;            // grid side, tile side, tiles per side
 };
 
+// Own cells of tile t to the grid, the rest of its region to its halo slot.
+template <typename R, int J>
+__device__ inline void store_region(const TileArgs<R> &a, const double *tre, const double *tim, int t, int tid,
+                                    int nthreads) {
+    const int T = a.T, K = a.K, RS = region_stride(T, J);
+    const int ta = (t / a.tps) * T, tb = (t % a.tps) * T;
+    for (int c = tid; c < T * T; c += nthreads) {
+        const int r = c / T, col = c - r * T;
+        a.grid[(int64_t)(ta + r) * K + tb + col] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    }
+    C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
+    for (int c = tid; c < T * (J - 1); c += nthreads) {  // right strip
+        const int r = c / (J - 1), col = T + c - r * (J - 1);
+        halo[c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    }
+    for (int c = tid; c < (J - 1) * (T + J - 1); c += nthreads) {  // bottom strip with the corner
+        const int r = T + c / (T + J - 1), col = c % (T + J - 1);
+        halo[T * (J - 1) + c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    }
+}
+
 // A tile's visibilities are one contiguous plan-order range; its wavefronts
-// take contiguous shares of it and work independently, 64 visibilities (a
-// slice) at a time.
+// take equal contiguous shares of it and work independently, at most 64
+// visibilities (a slice) at a time.
 //
 // Staging: lane t of the wavefront takes visibility t of the slice and writes
 // its J row weights times the value, and its J column weights shifted by the
@@ -426,27 +447,18 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     const int t = a.order[blockIdx.x];
     const int v0 = a.tile_start[t], total = a.tile_start[t + 1] - v0;
     const int ta = (t / tps) * T, tb = (t % tps) * T;
-    for (int c = tid; c < 2 * PS; c += kThreads) tre[c] = 0.0;
-    __syncthreads();
-
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, li = lane >> 3, lj = lane & 7;
-    C<R> *wuv = wuv_all + wave * JR * SR;
-    R *wv = wv_all + wave * NC * SR;
-    // Matrix path: row-weight rows J .. 7 are never staged and stay zero.
-    if constexpr (MF)
-        for (int i = J * SR + lane; i < JR * SR; i += 64) wuv[i] = mk<R>(0, 0);
-
-    // This wavefront's slices.
-    const int nsl = (total + 63) >> 6;
-    const int s_begin = (wave * nsl) / kWaves, s_end = ((wave + 1) * nsl) / kWaves;
+    // This wavefront's share of the tile's visibilities (tile-relative).
+    const int f_begin = (int)(((int64_t)wave * total) / kWaves);
+    const int f_end = (int)(((int64_t)(wave + 1) * total) / kWaves);
 
     // The visibility this lane stages next: cell, offsets and value.
     uint32_t cv = 0;
     R fu = 0, fv = 0;
     C<R> val = mk<R>(0, 0);
     auto load = [&](int f) {
-        if (f < total) {
+        if (f < f_end) {
             const int v = v0 + f;
             cv = a.cell[v];
             fu = a.frac[2 * (int64_t)v];
@@ -454,7 +466,16 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
             val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
         }
     };
-    if (s_begin < s_end) load(s_begin * 64 + lane);
+    // The first slice's loads are in flight while the region is cleared.
+    load(f_begin + lane);
+    for (int c = tid; c < 2 * PS; c += kThreads) tre[c] = 0.0;
+    __syncthreads();
+
+    C<R> *wuv = wuv_all + wave * JR * SR;
+    R *wv = wv_all + wave * NC * SR;
+    // Matrix path: row-weight rows J .. 7 are never staged and stay zero.
+    if constexpr (MF)
+        for (int i = J * SR + lane; i < JR * SR; i += 64) wuv[i] = mk<R>(0, 0);
 
     // Vector path state.
     int ic[NB], jc[QB];
@@ -505,9 +526,9 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     };
     int cur = -1;  // packed window row and column block of the open run (-1: none yet)
 
-    for (int sl = s_begin; sl < s_end; ++sl) {
-        const int base = sl * 64;
-        const bool live = base + lane < total;
+    for (int base = f_begin; base < f_end; base += 64) {
+        const int nlive = min(64, f_end - base);
+        const bool live = lane < nlive;
         // Staging.  Lanes past the end stage zero values, so the
         // accumulation below runs over all 64 entries without bound tests.
         if (!live) val = mk<R>(0, 0);
@@ -541,7 +562,7 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
         const uint64_t starts = __ballot(live && pos != prev);
         __builtin_amdgcn_wave_barrier();
         // The next slice's visibility: global loads in flight during the accumulation.
-        if (sl + 1 < s_end) load(base + 64 + lane);
+        load(base + 64 + lane);
 
         if constexpr (MF) {
             // Groups of 4 entries; a group holding run starts is split into
@@ -631,20 +652,7 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
         else close_run(cur);
     }
     __syncthreads();
-    // Own cells to the grid, the rest of the region to the halo slot.
-    for (int c = tid; c < T * T; c += kThreads) {
-        const int r = c / T, col = c - r * T;
-        a.grid[(int64_t)(ta + r) * K + tb + col] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
-    }
-    C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
-    for (int c = tid; c < T * (J - 1); c += kThreads) {  // right strip
-        const int r = c / (J - 1), col = T + c - r * (J - 1);
-        halo[c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
-    }
-    for (int c = tid; c < (J - 1) * (T + J - 1); c += kThreads) {  // bottom strip with the corner
-        const int r = T + c / (T + J - 1), col = c % (T + J - 1);
-        halo[T * (J - 1) + c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
-    }
+    store_region<R, J>(a, tre, tim, t, tid, kThreads);
 }
 
 // Adds to each tile's first J-1 rows and columns what the tiles above, to

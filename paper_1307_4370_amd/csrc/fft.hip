@@ -110,13 +110,22 @@ __device__ inline void stage(C<R> (&v)[E], int jt, int NE, int N, int Ns, const 
 #pragma unroll
         for (int r = 0; r < RR; ++r) x[r] = v[b + r * B];
         if (Ns > 1) {
-            const int step = N / (Ns * RR);
-#pragma unroll
-            for (int r = 1; r < RR; ++r) {
-                C<R> w = tw[r * k * step];
-                if (SGN > 0) w.y = -w.y;
-                x[r] = cmul<R>(x[r], w);
+            // One table twiddle per butterfly, w = exp(SGN 2 pi i k / (Ns RR));
+            // the others are its powers (products at most three deep), which
+            // spares the memory pipeline RR - 2 gathers per butterfly.
+            C<R> w[RR];
+            w[1] = tw[k * (N / (Ns * RR))];
+            if (SGN > 0) w[1].y = -w[1].y;
+            if constexpr (RR > 2) w[2] = cmul<R>(w[1], w[1]);
+            if constexpr (RR > 3) w[3] = cmul<R>(w[2], w[1]);
+            if constexpr (RR > 4) {
+                w[4] = cmul<R>(w[2], w[2]);
+                w[5] = cmul<R>(w[4], w[1]);
+                w[6] = cmul<R>(w[4], w[2]);
+                w[7] = cmul<R>(w[4], w[3]);
             }
+#pragma unroll
+            for (int r = 1; r < RR; ++r) x[r] = cmul<R>(x[r], w[r]);
         }
         Dft<R, RR, SGN>::run(x);
 #pragma unroll
@@ -124,7 +133,12 @@ __device__ inline void stage(C<R> (&v)[E], int jt, int NE, int N, int Ns, const 
     }
 }
 
-template <typename R, int E>
+// LDS slot of line position a.  SWZ (lines a multiple of 32 long): the low
+// five bits are XORed with bits 3..7, which spreads both the stride-RR
+// writes and the unit-stride reads of every exchange over all banks.
+template <bool SWZ> __device__ inline int lds_slot(int a) { return SWZ ? a ^ ((a >> 3) & 31) : a; }
+
+template <typename R, int E, bool SWZ = false>
 __device__ inline void exchange(C<R> (&v)[E], C<R> *lds, int ls, int jt, int NE, int Ns, int RR) {
     // v[b + r*B] holds output r of butterfly j = jt + b*NE, destined for
     // position (j - k) * RR + k + r * Ns with k = j mod Ns.
@@ -135,11 +149,11 @@ __device__ inline void exchange(C<R> (&v)[E], C<R> *lds, int ls, int jt, int NE,
         const int b = e % B, r = e / B;
         const int j = jt + b * NE;
         const int k = j % Ns;
-        lds[((j - k) * RR + k + r * Ns) * ls] = v[e];
+        lds[lds_slot<SWZ>((j - k) * RR + k + r * Ns) * ls] = v[e];
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = lds[(jt + e * NE) * ls];
+    for (int e = 0; e < E; ++e) v[e] = lds[lds_slot<SWZ>(jt + e * NE) * ls];
 }
 
 // Map line index i of a padded length-N line to its source index in [0, n),
@@ -151,10 +165,9 @@ __device__ inline int band_index(int i, int N, int n) {
     return -1;
 }
 
-// Row passes run 256-thread blocks; bounding single-precision radix-2^k lines
-// to 8 blocks per CU (64 registers) lets all K lines of a 2048-point pass be
-// resident at once.  Wider register sets keep fewer blocks so they do not spill.
-template <typename R, int E> constexpr int fft_row_blocks() { return E == 8 ? (sizeof(R) == 4 ? 8 : 4) : 2; }
+// Row passes run 256-thread blocks, at least 4 (radix-2^k lines) or 2 (wider
+// register sets) resident per CU.
+template <typename R, int E> constexpr int fft_row_blocks() { return E == 8 ? 4 : 2; }
 
 template <typename R, int E, int SGN, bool COLS>
 __global__ void __launch_bounds__(COLS ? 1024 : 256, COLS ? 1 : (fft_row_blocks<R, E>())) fft_pass(FftArgs<R> a) {
@@ -236,22 +249,32 @@ __global__ void __launch_bounds__(COLS ? 1024 : 256, COLS ? 1 : (fft_row_blocks<
 // then one radix-4 or radix-2 stage), so every index, stride and twiddle step
 // is a constant and k = j mod Ns is a mask.
 
+template <int N, int Ns> __host__ __device__ constexpr int p2_radix() {
+    return (N / Ns) % 8 == 0 ? 8 : (N / Ns) % 4 == 0 ? 4 : 2;
+}
 template <typename R, int E, int SGN, int N, int Ns>
 __device__ inline void p2_stages(C<R> (&v)[E], int jt, C<R> *lds, int ls, const C<R> *tw) {
-    constexpr int rem = N / Ns;
-    constexpr int RR = rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
-    constexpr int NE = N / E;
+    constexpr int RR = p2_radix<N, Ns>(), NE = N / E;
     stage<R, E, RR, SGN>(v, jt, NE, N, Ns, tw);
     if constexpr (Ns * RR < N) {
-        exchange<R, E>(v, lds, ls, jt, NE, Ns, RR);
+        exchange<R, E, (N % 32 == 0)>(v, lds, ls, jt, NE, Ns, RR);
         p2_stages<R, E, SGN, N, Ns * RR>(v, jt, lds, ls, tw);
     }
 }
 
+// The operator's four passes are fixed by (SGN, COLS), and the p2 kernel
+// specialises to them: forward passes read the padded line, whose n = N/2
+// inputs sit at line positions [0, N/4) and [3N/4, N), i.e. elements e < 2
+// and e >= 6 of every thread (elements 2..5 are zero and not loaded);
+// adjoint passes write only those positions; column passes carry the
+// gridding correction and 1/K (forward: on input, adjoint: on output).  Rows
+// are contiguous (element stride 1), columns adjacent (transform stride 1),
+// so every element offset is a 32-bit index.
 template <typename R, int LOGN, int SGN, bool COLS>
 __global__ void __launch_bounds__(COLS ? 1024 : 256, COLS ? 1 : (fft_row_blocks<R, 8>()))
 fft_pass_p2(FftArgs<R> a) {
     constexpr int N = 1 << LOGN, E = 8, NE = N / E;
+    constexpr bool FWD = SGN < 0;
     extern __shared__ unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
     int c, jt;
@@ -271,39 +294,47 @@ fft_pass_p2(FftArgs<R> a) {
     const bool active = t < a.nbatch;
     C<R> *lds = COLS ? smem + c : smem + (long)c * N;
     const int ls = COLS ? a.C : 1;
+    // Pixel index of band element e (e < 2 or e >= 6) of this thread.
+    auto band = [&](int e) { return e < 2 ? jt + e * NE + N / 4 : jt + e * NE - 3 * N / 4; };
 
+    const C<R> *src = COLS ? a.in + t : a.in + t * a.in_ts;
+    const int ies = COLS ? (int)a.in_es : 1;
     C<R> v[E];
-    const R tf = (active && a.dbt && a.factors_at_input) ? a.dbt[t] : R(1);
+    if constexpr (FWD) {
+        const R f0 = (COLS && active) ? a.scale * a.dbt[t] : R(1);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = jt + e * NE;
-        const int j = a.pad_in ? band_index(i, N, a.n) : i;
-        C<R> z = mk<R>(0, 0);
-        if (active && j >= 0) {
-            z = a.in[t * a.in_ts + (long)j * a.in_es];
-            if (a.factors_at_input) {
-                R f = a.scale * tf;
-                if (a.dax) f *= a.dax[j];
-                z = cscale<R>(z, f);
+        for (int e = 0; e < E; ++e) {
+            C<R> z = mk<R>(0, 0);
+            if (e < 2 || e >= 6) {
+                const int j = band(e);
+                if (active) {
+                    z = src[j * ies];
+                    if (COLS) z = cscale<R>(z, f0 * a.dax[j]);
+                }
             }
+            v[e] = z;
         }
-        v[e] = z;
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = active ? src[(jt + e * NE) * ies] : mk<R>(0, 0);
     }
     p2_stages<R, E, SGN, N, 1>(v, jt, lds, ls, a.tw);
     if (!active) return;
-    const R tf_out = (a.dbt && !a.factors_at_input) ? a.dbt[t] : R(1);
+    C<R> *dst = COLS ? a.out + t : a.out + t * a.out_ts;
+    const int oes = COLS ? (int)a.out_es : 1;
+    if constexpr (FWD) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = jt + e * NE;
-        const int j = a.crop_out ? band_index(i, N, a.n) : i;
-        if (j < 0) continue;
-        C<R> z = v[e];
-        if (!a.factors_at_input) {
-            R f = a.scale * tf_out;
-            if (a.dax) f *= a.dax[j];
-            z = cscale<R>(z, f);
+        for (int e = 0; e < E; ++e) dst[(jt + e * NE) * oes] = v[e];
+    } else {
+        const R f0 = COLS ? a.scale * a.dbt[t] : R(1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e >= 2 && e < 6) continue;
+            const int j = band(e);
+            C<R> z = v[e];
+            if (COLS) z = cscale<R>(z, f0 * a.dax[j]);
+            dst[j * oes] = z;
         }
-        a.out[t * a.out_ts + (long)j * a.out_es] = z;
     }
 }
 
@@ -380,12 +411,18 @@ static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
     a.C = Cb;
     const int threads = Cb * NE;
     RIOP_REQUIRE(threads <= 1024, RIOP_ENOTSUP, "FFT block too large");
+    const int N = f.N;
+    const bool pow2 = (N & (N - 1)) == 0 && N >= 16 && N <= 16384;
     const int blocks = (a.nbatch + Cb - 1) / Cb;
     const size_t lds = line * Cb;
     TimedScope ts(p, kind, st);
-    const int N = f.N;
-    const bool pow2 = (N & (N - 1)) == 0 && N >= 16 && N <= 16384;
     if (pow2 && E == 8) {
+        // The specialised kernel's layout and band assumptions (see above).
+        const bool fwd = SGN < 0;
+        RIOP_REQUIRE(2 * a.n == N && a.pad_in == (fwd ? 1 : 0) && a.crop_out == (fwd ? 0 : 1) &&
+                         (COLS ? (a.in_ts == 1 && a.out_ts == 1 && a.dax && a.dbt)
+                               : (a.in_es == 1 && a.out_es == 1 && !a.dax && !a.dbt && a.scale == R(1))),
+                     RIOP_EINVAL, "FFT pass layout not supported by the power-of-two kernel");
         switch (N) {
 #define P2(LG)                                                                                        \
     case 1 << LG:                                                                                     \

@@ -155,6 +155,7 @@ struct riop_plan {
     riop::DevBuf cell_start;  // int32[K^2 + 1]: plan-order start of each cell key
     riop::DevBuf tile_order;  // int32[ntiles]: tiles, heaviest first (gridding)
     riop::DevBuf halo;        // per tile: region cells outside the tile (gridding)
+    void *halo_pending = nullptr;  // grid last written by gridding, its tiles' halos not yet added
     int nunits = 0;
     int max_unit = 0;
 
@@ -206,6 +207,9 @@ void check_grid_lds(riop_plan *p);
 // Complex cells of one tile's gridding halo slot.
 inline int grid_halo_cells(int T, int J) { return T * (J - 1) + (J - 1) * (T + J - 1); }
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
+// Adds the gridding halos into `grid` (needed only where the adjoint FFT does
+// not add them while loading; see launch_phi_fft_adjoint).
+template <typename R> void launch_grid_merge(riop_plan *p, void *grid, hipStream_t st);
 template <typename R>
 void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st);
 template <typename R>

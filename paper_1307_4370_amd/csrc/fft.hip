@@ -28,6 +28,10 @@ template <typename R> struct FftArgs {
     const R *dbt;        // factor along the batch axis (nbatch entries), nullable
     long in_ts, in_es;   // strides (in complex elements) between transforms / elements
     long out_ts, out_es;
+    // Adjoint row pass of the power-of-two kernel: gridding halos to add on
+    // load (nullptr: none), with the gridding tile side, J and tiles per side.
+    const C<R> *halo;
+    int hT, hJ, htps;
     int N, nbatch, C, n;
     int pad_in, crop_out;
     int factors_at_input;
@@ -317,6 +321,60 @@ fft_pass_p2(FftArgs<R> a) {
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = active ? src[(jt + e * NE) * ies] : mk<R>(0, 0);
+        if constexpr (!COLS) {
+            // Gridding halos: a tile's first J - 1 rows and columns receive
+            // what the tiles above, to the left and above-left left in their
+            // halo slots (bottom strip (J - 1) x (T + J - 1) after a right
+            // strip T x (J - 1)), added in that order.  The row's left and
+            // above-left parts (J - 1 values per tile, at a stride W = 8 or
+            // 16 per tile) are first gathered into this row's LDS line, which
+            // the first exchange overwrites only after its leading barrier;
+            // host side: 2 W tps <= N, so each thread gathers at most 4.
+            if (a.halo) {
+                const int T = a.hT, J1 = a.hJ - 1, tps = a.htps, lt = __builtin_ctz(T);
+                const int lw = J1 <= 8 ? 3 : 4, NL = tps << lw;
+                const int HC = T * J1 + J1 * (T + J1);
+                const int k1 = (int)t, dr = k1 >> lt, i = k1 & (T - 1);
+                const int upr = dr == 0 ? tps - 1 : dr - 1;
+                const C<R> *hrow = a.halo + (long)dr * tps * HC + i * J1;                   // left parts
+                const C<R> *hup = a.halo + (long)upr * tps * HC + T * J1 + i * (T + J1);  // above, above-left
+                // The above tile's part (rows i < J - 1), loaded with the
+                // line so that the latencies overlap.
+                C<R> up[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int k2 = jt + e * NE, dc = k2 >> lt, j = k2 & (T - 1);
+                    up[e] = (active && i < J1) ? hup[dc * HC + j] : mk<R>(0, 0);
+                }
+                C<R> hl[4], hu[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int f = jt + q * NE, dc = f >> lw, j = f & ((1 << lw) - 1);
+                    const int lc = dc == 0 ? tps - 1 : dc - 1;
+                    const bool use = active && f < NL && j < J1;
+                    hl[q] = use ? hrow[lc * HC + j] : mk<R>(0, 0);
+                    hu[q] = (use && i < J1) ? hup[lc * HC + T + j] : mk<R>(0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int f = jt + q * NE;
+                    if (f < NL) {
+                        lds[f] = hl[q];
+                        lds[NL + f] = hu[q];
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int k2 = jt + e * NE, dc = k2 >> lt, j = k2 & (T - 1);
+                        if (i < J1) v[e] = cadd<R>(v[e], up[e]);
+                        if (j < J1) v[e] = cadd<R>(v[e], lds[(dc << lw) + j]);
+                        if (i < J1 && j < J1) v[e] = cadd<R>(v[e], lds[NL + (dc << lw) + j]);
+                    }
+                }
+            }
+        }
     }
     p2_stages<R, E, SGN, N, 1>(v, jt, lds, ls, a.tw);
     if (!active) return;
@@ -482,6 +540,22 @@ template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStre
     // Pass 1: rows k1 of grid, inverse transform over k2, keep the n cropped outputs.
     FftArgs<R> a{};
     a.in = grid ? static_cast<const C<R> *>(grid) : p->grid.as<C<R>>();
+    // A grid just written by gridding still lacks its tiles' halos: the
+    // specialised row pass adds them on load, otherwise they are merged first.
+    if (p->halo_pending) {
+        const int N = p->fft.N;
+        const bool p2 = (N & (N - 1)) == 0 && N >= 16 && N <= 16384 && p->fft.E == 8;
+        const int w = p->J - 1 <= 8 ? 8 : 16;
+        if (p2 && p->halo_pending == a.in && 2 * w * p->tiles_per_side <= N) {
+            a.halo = p->halo.as<C<R>>();
+            a.hT = p->tile;
+            a.hJ = p->J;
+            a.htps = p->tiles_per_side;
+        } else {
+            launch_grid_merge<R>(p, p->halo_pending, st);
+        }
+        p->halo_pending = nullptr;
+    }
     a.out = p->tmp.as<C<R>>();
     a.in_ts = K;
     a.in_es = 1;

@@ -414,8 +414,9 @@ __device__ inline void store_region(const TileArgs<R> &a, const double *tre, con
 // reads only what it staged itself.
 //
 // The workgroup finally stores its own T x T cells to the grid and the rest
-// of the region to its halo slot; grid_merge adds the halos of the three
-// neighbours a tile receives from.
+// of the region to its halo slot; the adjoint FFT's row pass adds the halos
+// of the three neighbours a tile receives from as it loads the grid (or
+// grid_merge does, where that pass is not the specialised one).
 // WAVES: grid_waves<R>(J), or 2 for tiles whose region leaves too little LDS.
 template <typename R, int J, bool USER, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
@@ -657,7 +658,9 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
 
 // Adds to each tile's first J-1 rows and columns what the tiles above, to
 // the left and above-left left in their halo slots (periodic in the tile
-// grid), in that fixed order.  One thread per border cell.
+// grid), in that fixed order.  One thread per border cell.  The adjoint FFT's
+// specialised row pass performs the same additions, in the same order, on
+// load; this kernel serves the other FFT lengths.
 template <typename R>
 __global__ void grid_merge(C<R> *grid, const C<R> *halo, int K, int T, int J, int tps) {
     const int per = (J - 1) * (2 * T - J + 1);  // border cells per tile
@@ -891,11 +894,17 @@ static void launch_tiles(riop_plan *p, const void *vals, int order_user, void *o
         default: throw Error{RIOP_ENOTSUP, "unsupported kernel width"};
     }
     RIOP_HIP(hipGetLastError());
+    // The halos are added by the adjoint FFT's first pass as it loads the grid.
+    p->halo_pending = out_grid;
+}
+
+template <typename R> void launch_grid_merge(riop_plan *p, void *grid, hipStream_t st) {
     const int64_t cells = (int64_t)p->ntiles * (p->J - 1) * (2 * p->tile - p->J + 1);
     if (cells > 0) {
+        TimedScope ts(p, KK_GRID, st);
         const int threads = 256;
         hipLaunchKernelGGL(grid_merge<R>, dim3((unsigned)((cells + threads - 1) / threads)), dim3(threads), 0, st,
-                           static_cast<C<R> *>(out_grid), (const C<R> *)p->halo.as<C<R>>(), p->K, p->tile, p->J,
+                           static_cast<C<R> *>(grid), (const C<R> *)p->halo.as<C<R>>(), p->K, p->tile, p->J,
                            p->tiles_per_side);
         RIOP_HIP(hipGetLastError());
     }
@@ -917,6 +926,8 @@ template void launch_degrid<float>(riop_plan *, void *, int, hipStream_t);
 template void launch_degrid<double>(riop_plan *, void *, int, hipStream_t);
 template void launch_grid<float>(riop_plan *, const void *, int, hipStream_t);
 template void launch_grid<double>(riop_plan *, const void *, int, hipStream_t);
+template void launch_grid_merge<float>(riop_plan *, void *, hipStream_t);
+template void launch_grid_merge<double>(riop_plan *, void *, hipStream_t);
 template void launch_fill_zero<float>(void *, size_t, hipStream_t);
 template void launch_fill_zero<double>(void *, size_t, hipStream_t);
 

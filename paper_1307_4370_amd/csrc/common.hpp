@@ -197,10 +197,30 @@ inline size_t rbytes(const riop_plan *p) { return p->prec == RIOP_F64 ? 8 : 4; }
 
 // Launch helpers implemented in the kernel translation units.  All take the
 // plan's real type as a template parameter and enqueue on `st`.
-template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st);
-// Adjoint FFT passes; `grid` selects the input grid (nullptr: the plan's grid).
+// CG steps the column FFT passes can fold in (CG on Q = Phi^dagger Phi + 2 I,
+// Sec. 4.4): before a forward transform of p, the direction update
+// p <- r + beta p with beta = sum(part[slot_new]) / sum(part[slot_old]) (0 when
+// the old sum is 0); after an adjoint transform into q, q <- q + 2 p with the
+// per-block partials of sum Re(conj(p) q) left in part[slot_pq].  `part` holds
+// nred doubles per slot.
+template <typename R> struct CgFuse {
+    const C<R> *r = nullptr;  // residual (direction update), nullable
+    const C<R> *p = nullptr;  // direction (p.q), nullable
+    double *part = nullptr;
+    int nred = 0, slot_old = 0, slot_new = 0, slot_pq = 0;
+};
+// Whether the column passes fold in the CG steps of CgFuse with nred partials
+// per slot (the power-of-two kernel with at most nred column blocks).
+bool fft_folds_cg(const riop_plan *p, int nred);
+// Forward FFT passes; returns whether cg->r's direction update was folded in
+// (false: the caller must apply it first; nothing was done).
 template <typename R>
-void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid = nullptr);
+bool launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st, const CgFuse<R> *cg = nullptr);
+// Adjoint FFT passes; `grid` selects the input grid (nullptr: the plan's grid).
+// Returns whether cg->p's q + 2 p and p.q partials were folded in.
+template <typename R>
+bool launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid = nullptr,
+                            const CgFuse<R> *cg = nullptr);
 // out_grid = G^T G in_grid (fused degrid + grid, the Gram part of Phi^dagger Phi).
 // Throws RIOP_ENOTSUP if the plan's gridding tile needs more LDS than the device has.
 void check_grid_lds(riop_plan *p);

@@ -32,6 +32,14 @@ template <typename R> struct FftArgs {
     // load (nullptr: none), with the gridding tile side, J and tiles per side.
     const C<R> *halo;
     int hT, hJ, htps;
+    // CG steps folded into the column passes (power-of-two kernel).  Forward:
+    // with cg_r set, the input p is replaced by r + beta p first and written
+    // back, beta = sum(cg_part[cg_new]) / sum(cg_part[cg_old]).  Adjoint: with
+    // cg_p set, the output q becomes q + 2 p and each block leaves its part of
+    // sum Re(conj(p) q) in cg_part[cg_pq] (cg_nred doubles per slot).
+    const C<R> *cg_r, *cg_p;
+    double *cg_part;
+    int cg_nred, cg_old, cg_new, cg_pq;
     int N, nbatch, C, n;
     int pad_in, crop_out;
     int factors_at_input;
@@ -158,6 +166,22 @@ __device__ inline void exchange(C<R> (&v)[E], C<R> *lds, int ls, int jt, int NE,
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = lds[lds_slot<SWZ>(jt + e * NE) * ls];
+}
+
+// Sum of one double per thread over the block, returned to every thread.
+// `red` holds at least blockDim.x / 64 doubles of LDS; brackets its use with
+// barriers.
+__device__ inline double block_sum_all(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    __syncthreads();
+    return s;
 }
 
 // Map line index i of a padded length-N line to its source index in [0, n),
@@ -306,6 +330,20 @@ fft_pass_p2(FftArgs<R> a) {
     C<R> v[E];
     if constexpr (FWD) {
         const R f0 = (COLS && active) ? a.scale * a.dbt[t] : R(1);
+        double beta = 0.0;
+        if constexpr (COLS) {
+            if (a.cg_r) {  // CG direction: beta = rr_new / rr_old (0 when rr_old = 0)
+                double so = 0.0, sn = 0.0;
+                for (int i = threadIdx.x; i < a.cg_nred; i += blockDim.x) {
+                    so += a.cg_part[a.cg_old * a.cg_nred + i];
+                    sn += a.cg_part[a.cg_new * a.cg_nred + i];
+                }
+                double *red = reinterpret_cast<double *>(smem);
+                so = block_sum_all(so, red);
+                sn = block_sum_all(sn, red);
+                beta = so == 0.0 ? 0.0 : sn / so;
+            }
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             C<R> z = mk<R>(0, 0);
@@ -313,7 +351,14 @@ fft_pass_p2(FftArgs<R> a) {
                 const int j = band(e);
                 if (active) {
                     z = src[j * ies];
-                    if (COLS) z = cscale<R>(z, f0 * a.dax[j]);
+                    if constexpr (COLS) {
+                        if (a.cg_r) {
+                            const C<R> r = a.cg_r[t + (long)j * ies];
+                            z = mk<R>((R)((double)r.x + beta * z.x), (R)((double)r.y + beta * z.y));
+                            const_cast<C<R> *>(a.in)[t + (long)j * ies] = z;
+                        }
+                        z = cscale<R>(z, f0 * a.dax[j]);
+                    }
                 }
             }
             v[e] = z;
@@ -377,21 +422,41 @@ fft_pass_p2(FftArgs<R> a) {
         }
     }
     p2_stages<R, E, SGN, N, 1>(v, jt, lds, ls, a.tw);
-    if (!active) return;
     C<R> *dst = COLS ? a.out + t : a.out + t * a.out_ts;
     const int oes = COLS ? (int)a.out_es : 1;
     if constexpr (FWD) {
+        if (!active) return;
 #pragma unroll
         for (int e = 0; e < E; ++e) dst[(jt + e * NE) * oes] = v[e];
     } else {
-        const R f0 = COLS ? a.scale * a.dbt[t] : R(1);
+        double acc = 0.0;  // CG: sum Re(conj(p) q) over this thread's outputs
+        if (active) {
+            const R f0 = COLS ? a.scale * a.dbt[t] : R(1);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            if (e >= 2 && e < 6) continue;
-            const int j = band(e);
-            C<R> z = v[e];
-            if (COLS) z = cscale<R>(z, f0 * a.dax[j]);
-            dst[j * oes] = z;
+            for (int e = 0; e < E; ++e) {
+                if (e >= 2 && e < 6) continue;
+                const int j = band(e);
+                C<R> z = v[e];
+                if constexpr (COLS) {
+                    z = cscale<R>(z, f0 * a.dax[j]);
+                    if (a.cg_p) {  // q + 2 p
+                        const C<R> pv = a.cg_p[t + (long)j * oes];
+                        z.x += R(2) * pv.x;
+                        z.y += R(2) * pv.y;
+                        acc += (double)pv.x * z.x + (double)pv.y * z.y;
+                    }
+                }
+                dst[j * oes] = z;
+            }
+        }
+        if constexpr (COLS) {
+            if (a.cg_p) {
+                acc = block_sum_all(acc, reinterpret_cast<double *>(smem));
+                double *slot = a.cg_part + (long)a.cg_pq * a.cg_nred;
+                if (threadIdx.x == 0) slot[blockIdx.x] = acc;
+                if (blockIdx.x == 0)  // entries past the grid's blocks
+                    for (int i = gridDim.x + threadIdx.x; i < a.cg_nred; i += blockDim.x) slot[i] = 0.0;
+            }
         }
     }
 }
@@ -400,6 +465,13 @@ fft_pass_p2(FftArgs<R> a) {
 // Host side.
 
 static int elems_per_thread(const FftPlan &f) { return f.E; }
+
+// Transforms per column-pass block: as many as 64 KB of LDS and 1024 threads
+// allow, at most 16.
+static int col_block_transforms(const FftPlan &f, size_t cbytes) {
+    const int Cb = (int)std::min<size_t>((64 * 1024) / (cbytes * (size_t)f.N), 1024 / (f.N / f.E));
+    return std::max(1, std::min(Cb, 16));
+}
 
 void build_fft_plan(riop_plan *p, hipStream_t st) {
     FftPlan &f = p->fft;
@@ -447,7 +519,7 @@ void build_fft_plan(riop_plan *p, hipStream_t st) {
 }
 
 template <typename R, int SGN, bool COLS>
-static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
+static bool launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
     const FftPlan &f = p->fft;
     a.N = f.N;
     a.nstages = f.nstages;
@@ -459,8 +531,7 @@ static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
     const size_t line = sizeof(C<R>) * (size_t)f.N;
     int Cb;
     if (COLS) {
-        Cb = (int)std::min<size_t>(lds_budget / line, 1024 / NE);
-        Cb = std::max(1, std::min(Cb, 16));
+        Cb = col_block_transforms(f, sizeof(C<R>));
     } else {
         Cb = std::max(1, 256 / NE);
         Cb = (int)std::max<size_t>(1, std::min<size_t>(Cb, lds_budget / line));
@@ -473,6 +544,13 @@ static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
     const bool pow2 = (N & (N - 1)) == 0 && N >= 16 && N <= 16384;
     const int blocks = (a.nbatch + Cb - 1) / Cb;
     const size_t lds = line * Cb;
+    // CG steps ride only on the power-of-two column kernel, with at most one
+    // partial per block.
+    bool fused = false;
+    if (a.cg_r || a.cg_p) {
+        fused = COLS && pow2 && E == 8 && blocks <= a.cg_nred;
+        if (!fused) a.cg_r = a.cg_p = nullptr;
+    }
     TimedScope ts(p, kind, st);
     if (pow2 && E == 8) {
         // The specialised kernel's layout and band assumptions (see above).
@@ -495,9 +573,19 @@ static void launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
         hipLaunchKernelGGL((fft_pass<R, 24, SGN, COLS>), dim3(blocks), dim3(threads), lds, st, a);
     }
     RIOP_HIP(hipGetLastError());
+    return fused;
 }
 
-template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st) {
+bool fft_folds_cg(const riop_plan *p, int nred) {
+    const FftPlan &f = p->fft;
+    const int N = f.N;
+    if ((N & (N - 1)) != 0 || N < 16 || N > 16384 || f.E != 8) return false;
+    const int Cb = col_block_transforms(f, cbytes(p));
+    return (p->n + Cb - 1) / Cb <= nred;
+}
+
+template <typename R>
+bool launch_phi_fft_forward(riop_plan *p, const void *x, hipStream_t st, const CgFuse<R> *cg) {
     const int n = p->n, K = p->K;
     const R *d = p->deapod.as<R>();
     // Pass 1: columns q of x, transform over p; pad, correct by d(p) d(q), scale 1/K.
@@ -516,7 +604,14 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
     a.dbt = d;
     a.factors_at_input = 1;
     a.scale = R(1) / R(K);
-    launch_pass<R, -1, true>(p, a, KK_FFT_FWD_COL, st);
+    if (cg && cg->r) {
+        a.cg_r = cg->r;
+        a.cg_part = cg->part;
+        a.cg_nred = cg->nred;
+        a.cg_old = cg->slot_old;
+        a.cg_new = cg->slot_new;
+    }
+    const bool fused = launch_pass<R, -1, true>(p, a, KK_FFT_FWD_COL, st);
     // Pass 2: rows k1 of tmp, transform over q (padded) -> grid row k1.
     FftArgs<R> b{};
     b.in = p->tmp.as<C<R>>();
@@ -532,9 +627,11 @@ template <typename R> void launch_phi_fft_forward(riop_plan *p, const void *x, h
     b.factors_at_input = 1;
     b.scale = R(1);
     launch_pass<R, -1, false>(p, b, KK_FFT_FWD_ROW, st);
+    return fused;
 }
 
-template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid) {
+template <typename R>
+bool launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *grid, const CgFuse<R> *cg) {
     const int n = p->n, K = p->K;
     const R *d = p->deapod.as<R>();
     // Pass 1: rows k1 of grid, inverse transform over k2, keep the n cropped outputs.
@@ -584,12 +681,19 @@ template <typename R> void launch_phi_fft_adjoint(riop_plan *p, void *x, hipStre
     b.dbt = d;
     b.factors_at_input = 0;
     b.scale = R(1) / R(K);
-    launch_pass<R, +1, true>(p, b, KK_FFT_ADJ_COL, st);
+    if (cg && cg->p) {
+        b.cg_p = cg->p;
+        b.cg_part = cg->part;
+        b.cg_nred = cg->nred;
+        b.cg_pq = cg->slot_pq;
+    }
+    return launch_pass<R, +1, true>(p, b, KK_FFT_ADJ_COL, st);
 }
 
-template void launch_phi_fft_forward<float>(riop_plan *, const void *, hipStream_t);
-template void launch_phi_fft_forward<double>(riop_plan *, const void *, hipStream_t);
-template void launch_phi_fft_adjoint<float>(riop_plan *, void *, hipStream_t, const void *);
-template void launch_phi_fft_adjoint<double>(riop_plan *, void *, hipStream_t, const void *);
+template bool launch_phi_fft_forward<float>(riop_plan *, const void *, hipStream_t, const CgFuse<float> *);
+template bool launch_phi_fft_forward<double>(riop_plan *, const void *, hipStream_t, const CgFuse<double> *);
+template bool launch_phi_fft_adjoint<float>(riop_plan *, void *, hipStream_t, const void *, const CgFuse<float> *);
+template bool launch_phi_fft_adjoint<double>(riop_plan *, void *, hipStream_t, const void *,
+                                             const CgFuse<double> *);
 
 }  // namespace riop

@@ -324,15 +324,37 @@ static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_
     VEC_LAUNCH(p, cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
                        w.qp.as<C<R>>(), w.r.as<C<R>>(), w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
     RIOP_HIP(hipGetLastError());
+    // Where the FFT's column passes can, they apply the direction update
+    // (before transforming p) and form q + 2 p with its p.q partials (after);
+    // otherwise the vector kernels do.  The direction of the last iteration is
+    // never needed and is not formed.
+    const bool fold = fft_folds_cg(p, kRedBlocks);
     int cur = SLOT_RR0;
     for (int k = 0; k < n_iter; ++k) {
         const int nxt = cur == SLOT_RR0 ? SLOT_RR1 : SLOT_RR0;
-        gram_sorted<R>(p, w.p.ptr, w.qp.ptr, s);
-        VEC_LAUNCH(p, cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
+        CgFuse<R> cg;
+        cg.part = part;
+        cg.nred = kRedBlocks;
+        cg.slot_pq = SLOT_PQ;
+        if (k > 0) {  // p = r + beta p, beta = rr[cur] / rr[previous]
+            if (fold) {
+                cg.r = w.r.as<C<R>>();
+                cg.slot_old = nxt;
+                cg.slot_new = cur;
+            } else {
+                VEC_LAUNCH(p, cg_direction<R>, RB(), RT(), 0, s, w.r.as<C<R>>(), w.p.as<C<R>>(), N,
+                           (const double *)part, nxt, cur);
+            }
+        }
+        if (fold) cg.p = w.p.as<C<R>>();
+        const bool d_done = launch_phi_fft_forward<R>(p, w.p.ptr, s, fold ? &cg : nullptr);
+        launch_gram<R>(p, p->grid.ptr, p->grid2.ptr, s);
+        const bool q_done = launch_phi_fft_adjoint<R>(p, w.qp.ptr, s, p->grid2.ptr, fold ? &cg : nullptr);
+        RIOP_REQUIRE(d_done == (fold && k > 0) && q_done == fold, RIOP_EDEVICE, "CG step folding mismatch");
+        if (!fold)
+            VEC_LAUNCH(p, cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
         VEC_LAUNCH(p, cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r.as<C<R>>(), w.p.as<C<R>>(),
                            w.qp.as<C<R>>(), N, part, cur, (int)SLOT_PQ, nxt);
-        VEC_LAUNCH(p, cg_direction<R>, RB(), RT(), 0, s, w.r.as<C<R>>(), w.p.as<C<R>>(), N,
-                           (const double *)part, cur, nxt);
         RIOP_HIP(hipGetLastError());
         cur = nxt;
     }

@@ -330,9 +330,19 @@ fft_pass_p2(FftArgs<R> a) {
     C<R> v[E];
     if constexpr (FWD) {
         const R f0 = (COLS && active) ? a.scale * a.dbt[t] : R(1);
-        double beta = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            v[e] = mk<R>(0, 0);
+            if ((e < 2 || e >= 6) && active) v[e] = src[band(e) * ies];
+        }
         if constexpr (COLS) {
-            if (a.cg_r) {  // CG direction: beta = rr_new / rr_old (0 when rr_old = 0)
+            if (a.cg_r) {
+                // CG direction p = r + beta p, beta = rr_new / rr_old (0 when
+                // rr_old = 0), reduced while the line's loads are in flight.
+                C<R> rv[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    rv[e] = ((e < 2 || e >= 6) && active) ? a.cg_r[t + (long)band(e) * ies] : mk<R>(0, 0);
                 double so = 0.0, sn = 0.0;
                 for (int i = threadIdx.x; i < a.cg_nred; i += blockDim.x) {
                     so += a.cg_part[a.cg_old * a.cg_nred + i];
@@ -341,27 +351,19 @@ fft_pass_p2(FftArgs<R> a) {
                 double *red = reinterpret_cast<double *>(smem);
                 so = block_sum_all(so, red);
                 sn = block_sum_all(sn, red);
-                beta = so == 0.0 ? 0.0 : sn / so;
-            }
-        }
+                const double beta = so == 0.0 ? 0.0 : sn / so;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            C<R> z = mk<R>(0, 0);
-            if (e < 2 || e >= 6) {
-                const int j = band(e);
-                if (active) {
-                    z = src[j * ies];
-                    if constexpr (COLS) {
-                        if (a.cg_r) {
-                            const C<R> r = a.cg_r[t + (long)j * ies];
-                            z = mk<R>((R)((double)r.x + beta * z.x), (R)((double)r.y + beta * z.y));
-                            const_cast<C<R> *>(a.in)[t + (long)j * ies] = z;
-                        }
-                        z = cscale<R>(z, f0 * a.dax[j]);
+                for (int e = 0; e < E; ++e) {
+                    if ((e < 2 || e >= 6) && active) {
+                        const C<R> z = v[e];
+                        v[e] = mk<R>((R)((double)rv[e].x + beta * z.x), (R)((double)rv[e].y + beta * z.y));
+                        const_cast<C<R> *>(a.in)[t + (long)band(e) * ies] = v[e];
                     }
                 }
             }
-            v[e] = z;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if ((e < 2 || e >= 6) && active) v[e] = cscale<R>(v[e], f0 * a.dax[band(e)]);
         }
     } else {
 #pragma unroll

@@ -512,15 +512,16 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     const int mk_ = lane >> 4, mi = lane & 15;
     const int abase = 2 * ((mi >> 1) * SR + mk_) + (mi & 1);  // float index into wuv
     const int bbase = mi * SR + mk_;                          // index into wv
+    const int coff = 2 * mk_ * RS + mi;                       // this lane's first cell of a run block
     auto close_run_mf = [&](int pos) {
-        const int la = pos >> 8, cb = (pos & 255) << 3;
+        const int c = (pos >> 8) * RS + ((pos & 255) << 3) + coff;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int i = 2 * mk_ + h;
-            if (i < J) {
-                const int c = (la + i) * RS + cb + mi;
-                __hip_atomic_fetch_add(tre + c, (double)dacc[2 * h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(tim + c, (double)dacc[2 * h + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (2 * mk_ + h < J) {
+                __hip_atomic_fetch_add(tre + c + h * RS, (double)dacc[2 * h], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(tim + c + h * RS, (double)dacc[2 * h + 1], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
         dacc = mf4{0.f, 0.f, 0.f, 0.f};

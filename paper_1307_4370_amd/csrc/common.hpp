@@ -153,7 +153,7 @@ struct riop_plan {
     riop::DevBuf tile_start;  // int32[ntiles + 1]
     riop::DevBuf units;       // WorkUnit[nunits] (degridding)
     riop::DevBuf cell_start;  // int32[K^2 + 1]: plan-order start of each cell key
-    riop::DevBuf tile_order;  // int32[ntiles]: tiles, heaviest first (gridding)
+    riop::DevBuf tile_order;  // WorkUnit[ntiles]: tiles with their visibility ranges, heaviest first (gridding)
     riop::DevBuf halo;        // per tile: region cells outside the tile (gridding)
     void *halo_pending = nullptr;  // grid last written by gridding, its tiles' halos not yet added
     int nunits = 0;

@@ -364,8 +364,7 @@ template <typename R> struct TileArgs {
     const uint32_t *cell;     // plan order: a0 | b0 << 16
     const R *frac;            // plan order: rho_u, rho_v
     const int *perm;          // plan order -> caller order
-    const int *tile_start;    // ntiles + 1 plan-order offsets
-    const int *order;         // tiles, heaviest first
+    const WorkUnit *order;    // tiles, heaviest first: (tile, first visibility, count)
     const C<R> *vin;          // values to grid
     const R *__restrict__ kc; // kernel coefficients [pair][even/odd][D/2 + 1]
     int K, T, tps;            // grid side, tile side, tiles per side
@@ -445,8 +444,18 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     if constexpr (!kScalarCoef)
         for (int i = tid; i < (J / 2) * 2 * KS; i += kThreads) kcl[i] = a.kc[i];
 
-    const int t = a.order[blockIdx.x];
-    const int v0 = a.tile_start[t], total = a.tile_start[t + 1] - v0;
+    const WorkUnit wk = a.order[blockIdx.x];
+    const int t = wk.tile, v0 = wk.start, total = wk.count;
+    if (total == 0) {  // an empty tile: zeros for its cells and its halo slot, no region
+        const int ta0 = (t / tps) * T, tb0 = (t % tps) * T;
+        for (int c = tid; c < T * T; c += kThreads) {
+            const int r = c / T;
+            a.grid[(int64_t)(ta0 + r) * K + tb0 + c - r * T] = mk<R>(0, 0);
+        }
+        C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
+        for (int c = tid; c < halo_cells(T, J); c += kThreads) halo[c] = mk<R>(0, 0);
+        return;
+    }
     const int ta = (t / tps) * T, tb = (t % tps) * T;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, li = lane >> 3, lj = lane & 7;
@@ -784,14 +793,17 @@ template <typename R> static void build_layout_t(riop_plan *p, const void *uv, h
         RIOP_HIP(hipMemcpyAsync(p->units.ptr, units.data(), sizeof(WorkUnit) * units.size(),
                                 hipMemcpyHostToDevice, st));
 
-    // Gridding: sort tiles, heaviest first.
+    // Gridding: sort tiles, heaviest first, each with its visibility range.
     std::vector<std::pair<int, int>> work(ntiles);
     for (int t = 0; t < ntiles; ++t) work[t] = {ts[t + 1] - ts[t], t};
     std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-    std::vector<int> order(ntiles);
-    for (int t = 0; t < ntiles; ++t) order[t] = work[t].second;
-    p->tile_order.alloc(sizeof(int) * ntiles);
-    RIOP_HIP(hipMemcpyAsync(p->tile_order.ptr, order.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, st));
+    std::vector<WorkUnit> order(ntiles);
+    for (int k = 0; k < ntiles; ++k) {
+        const int t = work[k].second;
+        order[k] = WorkUnit{t, ts[t], ts[t + 1] - ts[t], 0};
+    }
+    p->tile_order.alloc(sizeof(WorkUnit) * ntiles);
+    RIOP_HIP(hipMemcpyAsync(p->tile_order.ptr, order.data(), sizeof(WorkUnit) * ntiles, hipMemcpyHostToDevice, st));
     RIOP_HIP(hipStreamSynchronize(st));
 }
 
@@ -864,8 +876,7 @@ static void launch_tiles(riop_plan *p, const void *vals, int order_user, void *o
     a.cell = p->cell.as<uint32_t>();
     a.frac = p->frac.as<R>();
     a.perm = p->perm.as<int>();
-    a.tile_start = p->tile_start.as<int>();
-    a.order = p->tile_order.as<int>();
+    a.order = p->tile_order.as<WorkUnit>();
     a.vin = static_cast<const C<R> *>(vals);
     a.kc = p->kcoef_compact.as<R>();
     a.K = p->K;

@@ -94,7 +94,8 @@ def traffic_summary(fetch_dir, write_dir, probe_mib):
         out[counter] = dict(cal=cal, tile=t * cal, merge=m * cal, n_tile=len(tile), n_merge=len(merge),
                             probe_raw=max(copies) if copies else 0.0)
     total = sum(out[c]["tile"] + out[c]["merge"] for c in out)
-    lines = ["# HBM traffic of the FP32 gridding launch, 1024^2, M = 4194304, J = 8 (grid_tile + grid_merge)\n",
+    lines = ["# HBM traffic of the FP32 gridding launch, 1024^2, M = 4194304, J = 8 (grid_tile; grid_merge only where the "
+             "adjoint FFT does not add the halos itself)\n",
              "Commands (repository root on the MI355X host, one counter pass each):\n", "```",
              "cd /tmp && export TMPDIR=/tmp",
              f"timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o t -- "

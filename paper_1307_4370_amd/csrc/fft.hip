@@ -196,9 +196,13 @@ __device__ inline int band_index(int i, int N, int n) {
 // Row passes run 256-thread blocks, at least 4 (radix-2^k lines) or 2 (wider
 // register sets) resident per CU.
 template <typename R, int E> constexpr int fft_row_blocks() { return E == 8 ? 4 : 2; }
+// Column blocks: up to 1024 threads, 512 for the 24-element lines, whose
+// register sets would otherwise spill at 1024 threads (128 registers).
+template <int E> constexpr int fft_col_threads() { return E == 24 ? 512 : 1024; }
 
 template <typename R, int E, int SGN, bool COLS>
-__global__ void __launch_bounds__(COLS ? 1024 : 256, COLS ? 1 : (fft_row_blocks<R, E>())) fft_pass(FftArgs<R> a) {
+__global__ void __launch_bounds__(COLS ? fft_col_threads<E>() : 256, COLS ? 1 : (fft_row_blocks<R, E>()))
+    fft_pass(FftArgs<R> a) {
     extern __shared__ unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
     const int N = a.N;
@@ -471,7 +475,8 @@ static int elems_per_thread(const FftPlan &f) { return f.E; }
 // Transforms per column-pass block: as many as 64 KB of LDS and 1024 threads
 // allow, at most 16.
 static int col_block_transforms(const FftPlan &f, size_t cbytes) {
-    const int Cb = (int)std::min<size_t>((64 * 1024) / (cbytes * (size_t)f.N), 1024 / (f.N / f.E));
+    const int threads = f.E == 24 ? fft_col_threads<24>() : fft_col_threads<8>();
+    const int Cb = (int)std::min<size_t>((64 * 1024) / (cbytes * (size_t)f.N), threads / (f.N / f.E));
     return std::max(1, std::min(Cb, 16));
 }
 

@@ -161,14 +161,24 @@ __global__ void __launch_bounds__(256) dwt_analysis(AnaArgs<R> a) {
         }
     }
 
-    // Periodic extension; on the smallest levels the region can exceed 2s.
-    for (int r = ty; r < IR; r += 4) {
-        int gr = 2 * k0 + r;
-        while (gr >= s) gr -= s;
-        for (int c = tx; c < IR; c += 64) {
-            int gc = 2 * l0 + c;
-            while (gc >= s) gc -= s;
-            reg[r * IRM + c] = in[(long)gr * s + gc];
+    // Periodic extension (on the smallest levels the region can exceed 2s).
+    // The region is at most 2 TO + 14 <= 64 wide, so thread (ty, tx) stages
+    // column tx of rows ty, ty + 4, ...: all its loads are issued before any
+    // is stored, so their latencies overlap.
+    {
+        constexpr int RPT = (IRM + 3) / 4;
+        C<R> st[RPT];
+        const bool col = tx < IR;
+        const long gc = (2 * l0 + tx) % s;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = ty + 4 * i;
+            if (col && r < IR) st[i] = in[(long)((2 * k0 + r) % s) * s + gc];
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = ty + 4 * i;
+            if (col && r < IR) reg[r * IRM + tx] = st[i];
         }
     }
     __syncthreads();
@@ -268,16 +278,34 @@ __device__ inline void syn_tile(const SynArgs<R> &a, int bi, int i0, int j0, C<R
     const int n = a.n;
     const C<R> *plane = a.alpha + (long)a.plane[bi] * n * n;
     const C<R> *llsrc = a.coarsest ? nullptr : a.ll_in + bi * a.ll_in_bstride;
+    // The four sub-band regions, KR <= TO + 7 square (at most 3 entries per
+    // thread for 256 threads): all loads issued before any is stored.
+    constexpr int EPT = ((kTO + kMaxTaps / 2 - 1) * (kTO + kMaxTaps / 2 - 1) + 255) / 256;
+    C<R> vll[EPT], vlh[EPT], vhl[EPT], vhh[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int idx = threadIdx.x + q * blockDim.x;
+        if (idx < KR * KR) {
+            const int r = idx / KR, c = idx - r * KR;
+            int k = (kst + r) % half, l = (lst + c) % half;
+            if (k < 0) k += half;
+            if (l < 0) l += half;
+            vll[q] = a.coarsest ? plane[(long)k * n + l] : llsrc[(long)k * half + l];
+            vlh[q] = plane[(long)k * n + half + l];
+            vhl[q] = plane[(long)(half + k) * n + l];
+            vhh[q] = plane[(long)(half + k) * n + half + l];
+        }
+    }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < KR * KR; idx += blockDim.x) {
-        const int r = idx / KR, c = idx - r * KR;
-        int k = (kst + r) % half, l = (lst + c) % half;
-        if (k < 0) k += half;
-        if (l < 0) l += half;
-        LL[idx] = a.coarsest ? plane[(long)k * n + l] : llsrc[(long)k * half + l];
-        LH[idx] = plane[(long)k * n + half + l];
-        HL[idx] = plane[(long)(half + k) * n + l];
-        HH[idx] = plane[(long)(half + k) * n + half + l];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int idx = threadIdx.x + q * blockDim.x;
+        if (idx < KR * KR) {
+            LL[idx] = vll[q];
+            LH[idx] = vlh[q];
+            HL[idx] = vhl[q];
+            HH[idx] = vhh[q];
+        }
     }
     __syncthreads();
     // Columns (axis 0): lo1[ii][c] from (LL, HL), hi1[ii][c] from (LH, HH).

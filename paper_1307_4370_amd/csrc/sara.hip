@@ -165,7 +165,9 @@ __global__ void __launch_bounds__(256) dwt_analysis(AnaArgs<R> a) {
     // The region is at most 2 TO + 14 <= 64 wide, so thread (ty, tx) stages
     // column tx of rows ty, ty + 4, ...: all its loads are issued before any
     // is stored, so their latencies overlap.
-    {
+    // (Single precision; double-precision rows would spill registers and
+    // are staged one at a time.)
+    if constexpr (sizeof(R) == 4) {
         constexpr int RPT = (IRM + 3) / 4;
         C<R> st[RPT];
         const bool col = tx < IR;
@@ -179,6 +181,16 @@ __global__ void __launch_bounds__(256) dwt_analysis(AnaArgs<R> a) {
         for (int i = 0; i < RPT; ++i) {
             const int r = ty + 4 * i;
             if (col && r < IR) reg[r * IRM + tx] = st[i];
+        }
+    } else {
+        for (int r = ty; r < IR; r += 4) {
+            int gr = 2 * k0 + r;
+            while (gr >= s) gr -= s;
+            for (int c = tx; c < IR; c += 64) {
+                int gc = 2 * l0 + c;
+                while (gc >= s) gc -= s;
+                reg[r * IRM + c] = in[(long)gr * s + gc];
+            }
         }
     }
     __syncthreads();
@@ -262,49 +274,79 @@ template <typename R> struct SynArgs {
     R scale;
 };
 
-// Column then row synthesis of one (2 TO)^2 output tile of basis slot bi;
-// adds the result into acc (thread-owned outputs idx = threadIdx.x + k*blockDim).
+// The four sub-band regions of one synthesis tile, KR <= TO + 7 square: at
+// most 3 entries per thread for 256 threads, held in registers between their
+// loads and their LDS stores.
+constexpr int kSynEPT = ((kTO + kMaxTaps / 2 - 1) * (kTO + kMaxTaps / 2 - 1) + 255) / 256;
+template <typename R> struct SynRegion {
+    C<R> ll[kSynEPT], lh[kSynEPT], hl[kSynEPT], hh[kSynEPT];
+};
+
+// Issues the loads of basis slot bi's regions for the (2 TO)^2 output tile at (i0, j0).
 template <typename R>
-__device__ inline void syn_tile(const SynArgs<R> &a, int bi, int i0, int j0, C<R> *smem, C<R> (&acc)[4]) {
-    const int b = a.basis[bi];
-    const int Lf = 2 * b;
-    const R *h = a.filt + (b * 2 + 0) * kMaxTaps;
-    const R *g = a.filt + (b * 2 + 1) * kMaxTaps;
-    const int s = a.s, half = s >> 1, TO = a.TO, TS = 2 * TO;
-    const int KR = TO + Lf / 2 - 1;
+__device__ inline void syn_load(const SynArgs<R> &a, int bi, int i0, int j0, SynRegion<R> &v) {
+    const int Lf = 2 * a.basis[bi];
+    const int half = a.s >> 1, KR = a.TO + Lf / 2 - 1;
     const int kst = i0 / 2 - Lf / 2 + 1, lst = j0 / 2 - Lf / 2 + 1;
-    C<R> *LL = smem, *LH = LL + KR * KR, *HL = LH + KR * KR, *HH = HL + KR * KR;
-    C<R> *lo1 = HH + KR * KR, *hi1 = lo1 + TS * KR;
     const int n = a.n;
     const C<R> *plane = a.alpha + (long)a.plane[bi] * n * n;
     const C<R> *llsrc = a.coarsest ? nullptr : a.ll_in + bi * a.ll_in_bstride;
-    // The four sub-band regions, KR <= TO + 7 square (at most 3 entries per
-    // thread for 256 threads): all loads issued before any is stored.
-    constexpr int EPT = ((kTO + kMaxTaps / 2 - 1) * (kTO + kMaxTaps / 2 - 1) + 255) / 256;
-    C<R> vll[EPT], vlh[EPT], vhl[EPT], vhh[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
+    for (int q = 0; q < kSynEPT; ++q) {
         const int idx = threadIdx.x + q * blockDim.x;
         if (idx < KR * KR) {
             const int r = idx / KR, c = idx - r * KR;
             int k = (kst + r) % half, l = (lst + c) % half;
             if (k < 0) k += half;
             if (l < 0) l += half;
-            vll[q] = a.coarsest ? plane[(long)k * n + l] : llsrc[(long)k * half + l];
-            vlh[q] = plane[(long)k * n + half + l];
-            vhl[q] = plane[(long)(half + k) * n + l];
-            vhh[q] = plane[(long)(half + k) * n + half + l];
+            v.ll[q] = a.coarsest ? plane[(long)k * n + l] : llsrc[(long)k * half + l];
+            v.lh[q] = plane[(long)k * n + half + l];
+            v.hl[q] = plane[(long)(half + k) * n + l];
+            v.hh[q] = plane[(long)(half + k) * n + half + l];
         }
     }
-    __syncthreads();
+}
+
+// Column then row synthesis of one (2 TO)^2 output tile of basis slot bi from
+// its loaded regions; adds the result into acc (thread-owned outputs
+// idx = threadIdx.x + k*blockDim).
+template <typename R>
+__device__ inline void syn_tile(const SynArgs<R> &a, int bi, const SynRegion<R> *v, int i0, int j0, C<R> *smem,
+                                C<R> (&acc)[4]) {
+    const int b = a.basis[bi];
+    const int Lf = 2 * b;
+    const R *h = a.filt + (b * 2 + 0) * kMaxTaps;
+    const R *g = a.filt + (b * 2 + 1) * kMaxTaps;
+    const int TO = a.TO, TS = 2 * TO;
+    const int KR = TO + Lf / 2 - 1;
+    C<R> *LL = smem, *LH = LL + KR * KR, *HL = LH + KR * KR, *HH = HL + KR * KR;
+    C<R> *lo1 = HH + KR * KR, *hi1 = lo1 + TS * KR;
+    __syncthreads();  // the previous tile's readers of smem are done
+    if (v) {
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
-        if (idx < KR * KR) {
-            LL[idx] = vll[q];
-            LH[idx] = vlh[q];
-            HL[idx] = vhl[q];
-            HH[idx] = vhh[q];
+        for (int q = 0; q < kSynEPT; ++q) {
+            const int idx = threadIdx.x + q * blockDim.x;
+            if (idx < KR * KR) {
+                LL[idx] = v->ll[q];
+                LH[idx] = v->lh[q];
+                HL[idx] = v->hl[q];
+                HH[idx] = v->hh[q];
+            }
+        }
+    } else {  // regions read straight into LDS (double precision)
+        const int half = a.s >> 1, n = a.n;
+        const int kst = i0 / 2 - Lf / 2 + 1, lst = j0 / 2 - Lf / 2 + 1;
+        const C<R> *plane = a.alpha + (long)a.plane[bi] * n * n;
+        const C<R> *llsrc = a.coarsest ? nullptr : a.ll_in + bi * a.ll_in_bstride;
+        for (int idx = threadIdx.x; idx < KR * KR; idx += blockDim.x) {
+            const int r = idx / KR, c = idx - r * KR;
+            int k = (kst + r) % half, l = (lst + c) % half;
+            if (k < 0) k += half;
+            if (l < 0) l += half;
+            LL[idx] = a.coarsest ? plane[(long)k * n + l] : llsrc[(long)k * half + l];
+            LH[idx] = plane[(long)k * n + half + l];
+            HL[idx] = plane[(long)(half + k) * n + l];
+            HH[idx] = plane[(long)(half + k) * n + half + l];
         }
     }
     __syncthreads();
@@ -356,7 +398,13 @@ template <typename R> __global__ void __launch_bounds__(256) dwt_synthesis(SynAr
     const int i0 = (blockIdx.x / tiles) * TS, j0 = (blockIdx.x % tiles) * TS;
     C<R> acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = mk<R>(0, 0);
-    syn_tile<R>(a, bi, i0, j0, smem, acc);
+    if constexpr (sizeof(R) == 4) {
+        SynRegion<R> v;
+        syn_load<R>(a, bi, i0, j0, v);
+        syn_tile<R>(a, bi, &v, i0, j0, smem, acc);
+    } else {
+        syn_tile<R>(a, bi, nullptr, i0, j0, smem, acc);
+    }
     C<R> *out = a.ll_out + bi * a.ll_out_bstride;
     for (int q = 0; q < 4; ++q) {
         const int idx = threadIdx.x + q * blockDim.x;
@@ -374,7 +422,19 @@ template <typename R> __global__ void __launch_bounds__(256) dwt_synthesis_final
     const int i0 = (blockIdx.x / tiles) * TS, j0 = (blockIdx.x % tiles) * TS;
     C<R> acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = mk<R>(0, 0);
-    for (int bi = 0; bi < a.nbases; ++bi) syn_tile<R>(a, bi, i0, j0, smem, acc);
+    if constexpr (sizeof(R) == 4) {
+        // The next basis's regions load while the current one is filtered
+        // (single precision: double-precision regions would spill).
+        SynRegion<R> v, vn;
+        if (a.nbases > 0) syn_load<R>(a, 0, i0, j0, v);
+        for (int bi = 0; bi < a.nbases; ++bi) {
+            if (bi + 1 < a.nbases) syn_load<R>(a, bi + 1, i0, j0, vn);
+            syn_tile<R>(a, bi, &v, i0, j0, smem, acc);
+            v = vn;
+        }
+    } else {
+        for (int bi = 0; bi < a.nbases; ++bi) syn_tile<R>(a, bi, nullptr, i0, j0, smem, acc);
+    }
     const int n = a.n;
     for (int q = 0; q < 4; ++q) {
         const int idx = threadIdx.x + q * blockDim.x;

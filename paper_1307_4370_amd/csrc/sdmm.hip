@@ -65,6 +65,18 @@ __device__ inline double slot_sum(const double *partials, int slot) {
 
 #define GRID_LOOP(i, n) for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
 
+// Grid-stride loop over kU elements per thread per step: a thread's elements
+// are i0, i0 + stride, ..., the same order as GRID_LOOP, so per-thread sums are
+// unchanged.  The kernels below read all kU elements of a step before writing
+// any: their arrays may alias as far as the compiler knows, so it would not
+// move a later element's loads above an earlier one's stores, and one element
+// per thread in flight is too little to cover HBM latency.
+constexpr int kU = 4;
+#define CHUNK_LOOP(i0, st, n)                                                                  \
+    for (long st = (long)gridDim.x * blockDim.x, i0 = (long)blockIdx.x * blockDim.x + threadIdx.x; \
+         i0 < (n); i0 += kU * st)
+#define FOR_U(u) _Pragma("unroll") for (int u = 0; u < kU; ++u)
+
 template <typename R> __device__ inline double abs2(C<R> z) { return (double)z.x * z.x + (double)z.y * z.y; }
 
 // r = b - (Qx_partial + 2 x); p = r; slot <- sum |r|^2
@@ -72,12 +84,20 @@ template <typename R>
 __global__ void cg_init(const C<R> *b, const C<R> *x, const C<R> *ax, C<R> *r, C<R> *p, long N, double *partials,
                         int slot) {
     double acc = 0;
-    GRID_LOOP(i, N) {
-        const C<R> xi = x[i], ai = ax[i], bi = b[i];
-        const C<R> ri = mk<R>(bi.x - (ai.x + R(2) * xi.x), bi.y - (ai.y + R(2) * xi.y));
-        r[i] = ri;
-        p[i] = ri;
-        acc += abs2<R>(ri);
+    CHUNK_LOOP(i0, st, N) {
+        C<R> xv[kU], av[kU], bv[kU];
+        FOR_U(u) if (i0 + u * st < N) {
+            xv[u] = x[i0 + u * st];
+            av[u] = ax[i0 + u * st];
+            bv[u] = b[i0 + u * st];
+        }
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            const C<R> ri = mk<R>(bv[u].x - (av[u].x + R(2) * xv[u].x), bv[u].y - (av[u].y + R(2) * xv[u].y));
+            r[i] = ri;
+            p[i] = ri;
+            acc += abs2<R>(ri);
+        }
     }
     const double s = block_sum(acc);
     if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
@@ -86,13 +106,20 @@ __global__ void cg_init(const C<R> *b, const C<R> *x, const C<R> *ax, C<R> *r, C
 // qp <- qp + 2 p ; slot <- sum Re(conj(p) qp)
 template <typename R> __global__ void cg_pq(const C<R> *p, C<R> *qp, long N, double *partials, int slot) {
     double acc = 0;
-    GRID_LOOP(i, N) {
-        const C<R> pi = p[i];
-        C<R> q = qp[i];
-        q.x += R(2) * pi.x;
-        q.y += R(2) * pi.y;
-        qp[i] = q;
-        acc += (double)pi.x * q.x + (double)pi.y * q.y;
+    CHUNK_LOOP(i0, st, N) {
+        C<R> pv[kU], qv[kU];
+        FOR_U(u) if (i0 + u * st < N) {
+            pv[u] = p[i0 + u * st];
+            qv[u] = qp[i0 + u * st];
+        }
+        FOR_U(u) if (i0 + u * st < N) {
+            const C<R> pi = pv[u];
+            C<R> q = qv[u];
+            q.x += R(2) * pi.x;
+            q.y += R(2) * pi.y;
+            qp[i0 + u * st] = q;
+            acc += (double)pi.x * q.x + (double)pi.y * q.y;
+        }
     }
     const double s = block_sum(acc);
     if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
@@ -106,16 +133,26 @@ __global__ void cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long 
     const double pq = slot_sum(partials, slot_pq);
     const double alpha = (rr == 0.0 || pq == 0.0) ? 0.0 : rr / pq;
     double acc = 0;
-    GRID_LOOP(i, N) {
-        const C<R> pi = p[i], qi = qp[i];
-        C<R> xi = x[i], ri = r[i];
-        xi.x = (R)((double)xi.x + alpha * pi.x);
-        xi.y = (R)((double)xi.y + alpha * pi.y);
-        ri.x = (R)((double)ri.x - alpha * qi.x);
-        ri.y = (R)((double)ri.y - alpha * qi.y);
-        x[i] = xi;
-        r[i] = ri;
-        acc += abs2<R>(ri);
+    CHUNK_LOOP(i0, st, N) {
+        C<R> pv[kU], qv[kU], xv[kU], rv[kU];
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            pv[u] = p[i];
+            qv[u] = qp[i];
+            xv[u] = x[i];
+            rv[u] = r[i];
+        }
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            C<R> xi = xv[u], ri = rv[u];
+            xi.x = (R)((double)xi.x + alpha * pv[u].x);
+            xi.y = (R)((double)xi.y + alpha * pv[u].y);
+            ri.x = (R)((double)ri.x - alpha * qv[u].x);
+            ri.y = (R)((double)ri.y - alpha * qv[u].y);
+            x[i] = xi;
+            r[i] = ri;
+            acc += abs2<R>(ri);
+        }
     }
     __syncthreads();
     const double s = block_sum(acc);
@@ -128,9 +165,15 @@ __global__ void cg_direction(const C<R> *r, C<R> *p, long N, const double *parti
     const double rr_old = slot_sum(partials, slot_old);
     const double rr_new = slot_sum(partials, slot_new);
     const double beta = rr_old == 0.0 ? 0.0 : rr_new / rr_old;
-    GRID_LOOP(i, N) {
-        const C<R> ri = r[i], pi = p[i];
-        p[i] = mk<R>((R)((double)ri.x + beta * pi.x), (R)((double)ri.y + beta * pi.y));
+    CHUNK_LOOP(i0, st, N) {
+        C<R> rv[kU], pv[kU];
+        FOR_U(u) if (i0 + u * st < N) {
+            rv[u] = r[i0 + u * st];
+            pv[u] = p[i0 + u * st];
+        }
+        FOR_U(u) if (i0 + u * st < N) {
+            p[i0 + u * st] = mk<R>((R)((double)rv[u].x + beta * pv[u].x), (R)((double)rv[u].y + beta * pv[u].y));
+        }
     }
 }
 
@@ -181,12 +224,20 @@ template <typename R> __global__ void scatter_perm(const C<R> *src, const int *p
 template <typename R>
 __global__ void prox2_norms(const C<R> *s, const C<R> *z2, const C<R> *y, long M, double *partials) {
     double e = 0, nu = 0;
-    GRID_LOOP(i, M) {
-        const C<R> si = s[i], zi = z2[i], yi = y[i];
-        const double dr = (double)si.x + zi.x - yi.x, di = (double)si.y + zi.y - yi.y;
-        e += dr * dr + di * di;
-        const double fr = (double)yi.x - si.x, fi = (double)yi.y - si.y;
-        nu += fr * fr + fi * fi;
+    CHUNK_LOOP(i0, st, M) {
+        C<R> sv[kU], zv[kU], yv[kU];
+        FOR_U(u) if (i0 + u * st < M) {
+            sv[u] = s[i0 + u * st];
+            zv[u] = z2[i0 + u * st];
+            yv[u] = y[i0 + u * st];
+        }
+        FOR_U(u) if (i0 + u * st < M) {
+            const C<R> si = sv[u], zi = zv[u], yi = yv[u];
+            const double dr = (double)si.x + zi.x - yi.x, di = (double)si.y + zi.y - yi.y;
+            e += dr * dr + di * di;
+            const double fr = (double)yi.x - si.x, fi = (double)yi.y - si.y;
+            nu += fr * fr + fi * fi;
+        }
     }
     const double se = block_sum(e);
     const double sn = block_sum(nu);
@@ -204,13 +255,22 @@ __global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, l
     const double e = sqrt(slot_sum(partials, SLOT_E));
     const double eps = scalars[SC_EPS];
     const double sc = e > eps ? eps / e : 1.0;
-    GRID_LOOP(i, M) {
-        const C<R> si = s[i], zi = z2[i], yi = y[i];
-        const double vr = (double)si.x + zi.x, vi = (double)si.y + zi.y;
-        const double rr = yi.x + (vr - yi.x) * sc, ri = yi.y + (vi - yi.y) * sc;
-        const double znr = vr - rr, zni = vi - ri;
-        z2[i] = mk<R>((R)znr, (R)zni);
-        w2[i] = mk<R>((R)(rr - znr), (R)(ri - zni));
+    CHUNK_LOOP(i0, st, M) {
+        C<R> sv[kU], zv[kU], yv[kU];
+        FOR_U(u) if (i0 + u * st < M) {
+            sv[u] = s[i0 + u * st];
+            zv[u] = z2[i0 + u * st];
+            yv[u] = y[i0 + u * st];
+        }
+        FOR_U(u) if (i0 + u * st < M) {
+            const long i = i0 + u * st;
+            const C<R> si = sv[u], zi = zv[u], yi = yv[u];
+            const double vr = (double)si.x + zi.x, vi = (double)si.y + zi.y;
+            const double rr = yi.x + (vr - yi.x) * sc, ri = yi.y + (vi - yi.y) * sc;
+            const double znr = vr - rr, zni = vi - ri;
+            z2[i] = mk<R>((R)znr, (R)zni);
+            w2[i] = mk<R>((R)(rr - znr), (R)(ri - zni));
+        }
     }
 }
 
@@ -218,14 +278,23 @@ __global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, l
 // z3 <- v - r3; rhs = x1 + x2 + (r3 - z3).
 template <typename R>
 __global__ void prox3_rhs(const C<R> *xh, C<R> *z3, const C<R> *x1, const C<R> *x2, C<R> *rhs, long N) {
-    GRID_LOOP(i, N) {
-        const C<R> xi = xh[i], zi = z3[i];
-        const R vr = xi.x + zi.x, vi = xi.y + zi.y;
-        const R r3 = vr > R(0) ? vr : R(0);
-        const C<R> zn = mk<R>(vr - r3, vi);
-        z3[i] = zn;
-        const C<R> a = x1[i], b = x2[i];
-        rhs[i] = mk<R>(a.x + b.x + (r3 - zn.x), a.y + b.y - zn.y);
+    CHUNK_LOOP(i0, st, N) {
+        C<R> xv[kU], zv[kU], av[kU], bv[kU];
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            xv[u] = xh[i];
+            zv[u] = z3[i];
+            av[u] = x1[i];
+            bv[u] = x2[i];
+        }
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            const R vr = xv[u].x + zv[u].x, vi = xv[u].y + zv[u].y;
+            const R r3 = vr > R(0) ? vr : R(0);
+            const C<R> zn = mk<R>(vr - r3, vi);
+            z3[i] = zn;
+            rhs[i] = mk<R>(av[u].x + bv[u].x + (r3 - zn.x), av[u].y + bv[u].y - zn.y);
+        }
     }
 }
 

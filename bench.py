@@ -134,11 +134,10 @@ def algorithmic_bytes(kind: str, n: int, M: int, cbytes: int):
       degrid:      read the grid 4N + (u, v) M, write y M            -> 4N + 2M
       grid:        read (u, v) M + values M, write the grid 4N       -> 4N + 2M
       grid_zero:   write the grid 4N
-      gram:        fused G^T G in CG: read the grid 4N + (u, v) M, write the grid 4N
     """
     N = n * n
     table = {"fft_fwd_col": 3 * N, "fft_fwd_row": 6 * N, "fft_adj_row": 6 * N, "fft_adj_col": 3 * N,
-             "degrid": 4 * N + 2 * M, "grid": 4 * N + 2 * M, "grid_zero": 4 * N, "gram": 8 * N + M}
+             "degrid": 4 * N + 2 * M, "grid": 4 * N + 2 * M, "grid_zero": 4 * N}
     return table[kind] * cbytes if kind in table else None
 
 

@@ -102,7 +102,7 @@ struct FftPlan {
 // Kernel kinds for event timing.
 enum KernelKind {
     KK_FFT_FWD_COL = 0, KK_FFT_FWD_ROW, KK_FFT_ADJ_ROW, KK_FFT_ADJ_COL,
-    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_GRAM, KK_COUNT
+    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_COUNT
 };
 
 struct Timing {

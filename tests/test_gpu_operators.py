@@ -205,6 +205,27 @@ def test_sara_parity(prec, n, levels, mask):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("n,M,J,tile", [(32, 5, 6, 8), (48, 700, 6, 16), (64, 4000, 6, 32), (96, 3001, 8, 64),
+                                        (128, 5000, 8, 32), (72, 2500, 8, 16)])
+def test_gram_matches_degrid_then_grid(prec, n, M, J, tile):
+    """Q x through the CG operator path (G^T G without the caller-order
+    permutation) against Phi then Phi^dagger in plan order plus 2 x, element
+    by element, and against the oracle.  Sizes span several tiles, empty tiles
+    (M = 5) and tiles whose region needs the two-wavefront layout (64 x 64)."""
+    device()
+    announce(f"gram n={n} M={M} J={J} tile={tile} {prec}")
+    uv, x, _ = _inputs(n, M, prec, 12)
+    plan = _plan(n, uv, J, prec, tile=tile)
+    xd = to_dev(x, prec)
+    q = host(plan.apply_q(xd))
+    split = host(plan.phi_adj(plan.phi(xd, sorted=True), sorted=True) + 2 * xd)
+    scale = max(float(np.abs(split).max()), 1e-300)
+    assert float(np.abs(q - split).max()) <= (1e-6 if prec == "f32" else 1e-14) * scale
+    op = nufft.Operator(n, uv, J)
+    assert rel(q, op.phi_adj(op.phi(x)) + 2 * x) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_apply_q_cg_and_gamma(prec):
     n, M, J, levels = 64, 4000, 8, 3
     device()

@@ -9,6 +9,12 @@
 // and every consumer block adds the slot's partials in the same fixed order.
 // Visibility-length vectors (y, z2, Phi x) are kept in plan order, so Phi and
 // Phi^dagger inside the loop avoid the permutation to the caller's order.
+//
+// Between iterations s2 holds Phi xhat (plan order): step 8 forms it for the
+// l2-ball prox, and the next CG, warm-started from the same xhat, takes its
+// initial residual from Phi^dagger s2 instead of applying Phi again (the same
+// kernels on the same values, so the result is unchanged).  The
+// initialisation establishes it for the starting xhat.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -383,13 +389,31 @@ template <typename R> static void gram_sorted(riop_plan *p, const void *x, void 
     launch_phi_fft_adjoint<R>(p, out, s, p->grid2.ptr);
 }
 
+// out = Phi^dagger y for y in plan order.
+template <typename R> static void phi_adj_sorted(riop_plan *p, const void *y, void *out, hipStream_t s) {
+    launch_grid<R>(p, y, 0, s);
+    launch_phi_fft_adjoint<R>(p, out, s);
+}
+
+// s2 = Phi x in plan order.
+template <typename R> static void phi_into_s2(riop_plan *p, const void *x, hipStream_t s) {
+    launch_phi_fft_forward<R>(p, x, s);
+    launch_degrid<R>(p, p->sd.s2.ptr, 0, s);
+}
+
+// CG on Q from x; phi_x (nullable) is Phi x in plan order, which saves the
+// forward half of the initial residual's Q x.
 template <typename R>
-static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_slot, hipStream_t s) {
+static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_slot, hipStream_t s,
+                   const void *phi_x = nullptr) {
     ensure_work(p);
     SdmmWork &w = p->sd;
     const long N = (long)p->n * p->n;
     double *part = w.partials.as<double>();
-    gram_sorted<R>(p, x, w.qp.ptr, s);
+    if (phi_x)
+        phi_adj_sorted<R>(p, phi_x, w.qp.ptr, s);
+    else
+        gram_sorted<R>(p, x, w.qp.ptr, s);
     VEC_LAUNCH(p, cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
                        w.qp.as<C<R>>(), w.r.as<C<R>>(), w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
     RIOP_HIP(hipGetLastError());
@@ -480,6 +504,7 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             VEC_LAUNCH(p, gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(prm->z2),
                        p->perm.as<int>(), w.z2loc.as<C<R>>(), M);
         VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, prm->f1_prev);
+        phi_into_s2<R>(p, xh, s);
     } else {
         // z_i = 0, r_i = L_i x0, x_i = L_i^dagger r_i.
         launch_fill_zero<R>(w.z1loc.ptr, D, s);
@@ -489,12 +514,14 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             RIOP_HIP(hipMemcpyAsync(xh, x0, cb * N, hipMemcpyDeviceToDevice, s));
             launch_psi_adj<R>(p, xh, w.w1.ptr, s);
             launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
-            gram_sorted<R>(p, xh, w.tmpN.ptr, s);
+            phi_into_s2<R>(p, xh, s);
+            phi_adj_sorted<R>(p, w.s2.ptr, w.tmpN.ptr, s);
             VEC_LAUNCH(p, add3<R>, RB(), RT(), 0, s, w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), (const C<R> *)xh,
                        w.rhs.as<C<R>>(), N);
         } else {
             launch_fill_zero<R>(xh, N, s);
             launch_fill_zero<R>(w.rhs.ptr, N, s);
+            launch_fill_zero<R>(w.s2.ptr, std::max<long>(1, M), s);  // Phi 0
         }
         VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, 0.0);
     }
@@ -517,13 +544,12 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
     for (int t = 0; t < iters; ++t) {
         // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x.
         int rr_slot = SLOT_RR0;
-        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s);
+        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s, w.s2.ptr);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
         launch_psi_adj_prox<R>(p, xh, px, s);
         launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
         // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2).
-        launch_phi_fft_forward<R>(p, xh, s);
-        launch_degrid<R>(p, w.s2.ptr, 0, s);
+        phi_into_s2<R>(p, xh, s);
         VEC_LAUNCH(p, prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(), w.ysort.as<C<R>>(),
                    M, part);
         if (M > 0)

@@ -10,11 +10,14 @@
 // Visibility-length vectors (y, z2, Phi x) are kept in plan order, so Phi and
 // Phi^dagger inside the loop avoid the permutation to the caller's order.
 //
-// Between iterations s2 holds Phi xhat (plan order): step 8 forms it for the
-// l2-ball prox, and the next CG, warm-started from the same xhat, takes its
-// initial residual from Phi^dagger s2 instead of applying Phi again (the same
-// kernels on the same values, so the result is unchanged).  The
-// initialisation establishes it for the starting xhat.
+// The CG of step 5 is warm-started from the previous xhat, so its initial
+// residual is b - Phi^dagger Phi xhat - 2 xhat with b = x1 + x2 + x3 and
+// x2 = Phi^dagger w2.  Since Phi xhat is at hand (step 8 forms it, s2, for the
+// l2-ball prox), the state keeps rhs = b - Phi^dagger Phi xhat =
+// x1 + x3 + Phi^dagger (w2 - s2): one Phi^dagger per iteration instead of a
+// Phi/Phi^dagger pair plus Phi^dagger w2, and the difference is taken in the
+// visibility domain.  The initialisation sets it for the starting xhat;
+// b itself is formed only for the exported state (rhs + Phi^dagger s2).
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -85,7 +88,7 @@ constexpr int kU = 4;
 
 template <typename R> __device__ inline double abs2(C<R> z) { return (double)z.x * z.x + (double)z.y * z.y; }
 
-// r = b - (Qx_partial + 2 x); p = r; slot <- sum |r|^2
+// r = b - (Qx_partial + 2 x); p = r; slot <- sum |r|^2 (ax null: Qx_partial = 0)
 template <typename R>
 __global__ void cg_init(const C<R> *b, const C<R> *x, const C<R> *ax, C<R> *r, C<R> *p, long N, double *partials,
                         int slot) {
@@ -94,7 +97,7 @@ __global__ void cg_init(const C<R> *b, const C<R> *x, const C<R> *ax, C<R> *r, C
         C<R> xv[kU], av[kU], bv[kU];
         FOR_U(u) if (i0 + u * st < N) {
             xv[u] = x[i0 + u * st];
-            av[u] = ax[i0 + u * st];
+            av[u] = ax ? ax[i0 + u * st] : mk<R>(0, 0);
             bv[u] = b[i0 + u * st];
         }
         FOR_U(u) if (i0 + u * st < N) {
@@ -254,7 +257,7 @@ __global__ void prox2_norms(const C<R> *s, const C<R> *z2, const C<R> *y, long M
 }
 
 // prox2 pass 2: v = s + z2; r2 = y + (v - y) min(1, eps/||v - y||);
-// z2 <- v - r2; w2 = r2 - z2 (input of Phi^dagger).
+// z2 <- v - r2; d2 = (r2 - z2) - s, the input of Phi^dagger (w2 less Phi xhat).
 template <typename R>
 __global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, long M, const double *partials,
                              const double *scalars) {
@@ -275,7 +278,7 @@ __global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, l
             const double rr = yi.x + (vr - yi.x) * sc, ri = yi.y + (vi - yi.y) * sc;
             const double znr = vr - rr, zni = vi - ri;
             z2[i] = mk<R>((R)znr, (R)zni);
-            w2[i] = mk<R>((R)(rr - znr), (R)(ri - zni));
+            w2[i] = mk<R>((R)(rr - znr - si.x), (R)(ri - zni - si.y));
         }
     }
 }
@@ -304,11 +307,11 @@ __global__ void prox3_rhs(const C<R> *xh, C<R> *z3, const C<R> *x1, const C<R> *
     }
 }
 
-// rhs = a + b + c
-template <typename R> __global__ void add3(const C<R> *a, const C<R> *b, const C<R> *c, C<R> *out, long N) {
+// out = a + sb b (sb = +1 or -1)
+template <typename R> __global__ void lin2(const C<R> *a, const C<R> *b, R sb, C<R> *out, long N) {
     GRID_LOOP(i, N) {
-        const C<R> x = a[i], y = b[i], z = c[i];
-        out[i] = mk<R>(x.x + y.x + z.x, x.y + y.y + z.y);
+        const C<R> x = a[i], y = b[i];
+        out[i] = mk<R>(x.x + sb * y.x, x.y + sb * y.y);
     }
 }
 
@@ -401,21 +404,18 @@ template <typename R> static void phi_into_s2(riop_plan *p, const void *x, hipSt
     launch_degrid<R>(p, p->sd.s2.ptr, 0, s);
 }
 
-// CG on Q from x; phi_x (nullable) is Phi x in plan order, which saves the
-// forward half of the initial residual's Q x.
+// CG on Q from x.  b_less_gram: b already has Phi^dagger Phi x subtracted.
 template <typename R>
 static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_slot, hipStream_t s,
-                   const void *phi_x = nullptr) {
+                   bool b_less_gram = false) {
     ensure_work(p);
     SdmmWork &w = p->sd;
     const long N = (long)p->n * p->n;
     double *part = w.partials.as<double>();
-    if (phi_x)
-        phi_adj_sorted<R>(p, phi_x, w.qp.ptr, s);
-    else
-        gram_sorted<R>(p, x, w.qp.ptr, s);
+    if (!b_less_gram) gram_sorted<R>(p, x, w.qp.ptr, s);
     VEC_LAUNCH(p, cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
-                       w.qp.as<C<R>>(), w.r.as<C<R>>(), w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
+                       b_less_gram ? (const C<R> *)nullptr : (const C<R> *)w.qp.as<C<R>>(), w.r.as<C<R>>(),
+                       w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
     RIOP_HIP(hipGetLastError());
     // Where the FFT's column passes can, they apply the direction update
     // (before transforming p) and form q + 2 p with its p.q partials (after);
@@ -504,7 +504,11 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             VEC_LAUNCH(p, gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(prm->z2),
                        p->perm.as<int>(), w.z2loc.as<C<R>>(), M);
         VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, prm->f1_prev);
+        // rhs <- b - Phi^dagger Phi xhat
         phi_into_s2<R>(p, xh, s);
+        phi_adj_sorted<R>(p, w.s2.ptr, w.tmpN.ptr, s);
+        VEC_LAUNCH(p, lin2<R>, RB(), RT(), 0, s, (const C<R> *)w.rhs.as<C<R>>(), (const C<R> *)w.tmpN.as<C<R>>(),
+                   R(-1), w.rhs.as<C<R>>(), N);
     } else {
         // z_i = 0, r_i = L_i x0, x_i = L_i^dagger r_i.
         launch_fill_zero<R>(w.z1loc.ptr, D, s);
@@ -514,14 +518,14 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             RIOP_HIP(hipMemcpyAsync(xh, x0, cb * N, hipMemcpyDeviceToDevice, s));
             launch_psi_adj<R>(p, xh, w.w1.ptr, s);
             launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+            // x2 = Phi^dagger Phi x0 cancels against the warm start: rhs = x1 + x0.
             phi_into_s2<R>(p, xh, s);
-            phi_adj_sorted<R>(p, w.s2.ptr, w.tmpN.ptr, s);
-            VEC_LAUNCH(p, add3<R>, RB(), RT(), 0, s, w.x1.as<C<R>>(), w.tmpN.as<C<R>>(), (const C<R> *)xh,
+            VEC_LAUNCH(p, lin2<R>, RB(), RT(), 0, s, (const C<R> *)w.x1.as<C<R>>(), (const C<R> *)xh, R(1),
                        w.rhs.as<C<R>>(), N);
         } else {
             launch_fill_zero<R>(xh, N, s);
             launch_fill_zero<R>(w.rhs.ptr, N, s);
-            launch_fill_zero<R>(w.s2.ptr, std::max<long>(1, M), s);  // Phi 0
+            launch_fill_zero<R>(w.s2.ptr, std::max<long>(1, M), s);  // Phi 0 (for the exported b)
         }
         VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_F1PREV, 0.0);
     }
@@ -544,11 +548,12 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
     for (int t = 0; t < iters; ++t) {
         // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x.
         int rr_slot = SLOT_RR0;
-        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s, w.s2.ptr);
+        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s, true);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
         launch_psi_adj_prox<R>(p, xh, px, s);
         launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
-        // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2).
+        // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2),
+        // taken as Phi^dagger (r2 - z2 - Phi xhat) for the next warm start.
         phi_into_s2<R>(p, xh, s);
         VEC_LAUNCH(p, prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(), w.ysort.as<C<R>>(),
                    M, part);
@@ -579,7 +584,11 @@ static void sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, 
     if (x_out) RIOP_HIP(hipMemcpyAsync(x_out, w.xhat.ptr, cb * N, hipMemcpyDeviceToDevice, s));
     if (prm && prm->z1) RIOP_HIP(hipMemcpyAsync(prm->z1, w.z1loc.ptr, cb * D, hipMemcpyDeviceToDevice, s));
     if (prm && prm->z3) RIOP_HIP(hipMemcpyAsync(prm->z3, w.z3loc.ptr, cb * N, hipMemcpyDeviceToDevice, s));
-    if (prm && prm->rhs) RIOP_HIP(hipMemcpyAsync(prm->rhs, w.rhs.ptr, cb * N, hipMemcpyDeviceToDevice, s));
+    if (prm && prm->rhs) {  // b = rhs + Phi^dagger Phi xhat
+        phi_adj_sorted<R>(p, w.s2.ptr, w.tmpN.ptr, s);
+        VEC_LAUNCH(p, lin2<R>, RB(), RT(), 0, s, (const C<R> *)w.rhs.as<C<R>>(), (const C<R> *)w.tmpN.as<C<R>>(),
+                   R(1), static_cast<C<R> *>(prm->rhs), N);
+    }
     if (prm && prm->z2 && M > 0)
         VEC_LAUNCH(p, scatter_perm<R>, RB(), RT(), 0, s, (const C<R> *)w.z2loc.as<C<R>>(), p->perm.as<int>(),
                    static_cast<C<R> *>(prm->z2), M);

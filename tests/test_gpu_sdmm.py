@@ -54,6 +54,7 @@ def test_sdmm_small_matches_oracle(prec, tol):
     assert rel(host(gstate["z1"]), st.z1) <= tol * 10
     assert rel(host(gstate["z2"]), st.z2) <= tol * 10
     assert rel(host(gstate["z3"]), st.z3) <= tol * 10
+    assert rel(host(gstate["rhs"]), st.rhs) <= tol * 10
     for t in range(1, c.T):
         f1, zeta, nu, _ = ghist[t]
         assert f1 == pytest.approx(hist[t]["f1"], rel=tol)
@@ -76,6 +77,32 @@ def test_sdmm_config1_fixed_iterations(prec, tol):
     snr_g = osdmm.snr_db(x_true, np.real(host(xg)))
     assert snr_g == pytest.approx(snr_o, abs=0.01)
     assert ghist[-1][2] == pytest.approx(hist[-1]["nu"], rel=tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("T", [0, 3])
+def test_sdmm_from_x0_matches_oracle(prec, tol, T):
+    """Steps 1-3 from a given x0 (r_i = L_i x0, x_i = L_i^dagger r_i) and T
+    iterations after them: iterate and exported state (z_i and the right-hand
+    side sum_i x_i) against the oracle."""
+    device()
+    announce(f"sdmm from x0 {prec} T={T}")
+    c = SMALL
+    x_true, uv, op, y, eps = _problem(c, prec)
+    sara = wavelets.Sara(c.n, c.levels)
+    x0 = np.real(x_true) * 0.5 + 0.1 * W.random_complex((c.n, c.n), W.rng(c.cfg, 77))
+    if prec == "f32":
+        x0 = x0.astype(np.complex64).astype(np.complex128)
+    xo, st, _, _ = osdmm.sdmm(y, eps, op, sara, T=T, n_cg=8, gamma=0.01, x0=x0)
+    plan = _plan(c, uv, prec)
+    xg, stats, _, gstate = plan.sdmm(to_dev(y, prec), eps, T=T, n_cg=8, gamma=0.01, x0=to_dev(x0, prec))
+    assert stats["iters"] == T
+    assert rel(host(xg), xo) <= tol
+    assert rel(host(gstate["rhs"]), st.rhs) <= tol * 10
+    if T:
+        assert rel(host(gstate["z1"]), st.z1) <= tol * 10
+        assert rel(host(gstate["z2"]), st.z2) <= tol * 10
+        assert rel(host(gstate["z3"]), st.z3) <= tol * 10
 
 
 def test_sdmm_resume_equals_single_run():

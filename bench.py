@@ -236,7 +236,7 @@ def batch_vs_plain(steps, ncg, dev):
     t_batch = time.perf_counter() - a
     diff = max(float(torch.linalg.vector_norm(b - q) / max(float(torch.linalg.vector_norm(q)), 1e-300))
                for b, q in zip(xb, xp))
-    pairs = sum(Ms) * (ncg + 2) * steps
+    pairs = sum(Ms) * (ncg + 1) * steps
     out = {"channels": len(chans), "visibilities": sum(Ms), "sides": sorted({n for n, _, _ in chans}),
            "steps": steps, "n_cg": ncg,
            "batch_visibilities_per_s": pairs / t_batch, "plain_visibilities_per_s": pairs / t_plain,
@@ -342,10 +342,12 @@ def main():
         del bt
     ms_step = min(ms_stream, ms_graph) if ms_graph else ms_stream
     launch = "hip graph replay" if ms_graph and ms_graph <= ms_stream else "stream launches"
-    # The method's count: n_cg + 1 pairs in CG (warm start) and one in steps 7-9.
-    # The library runs n_cg + 1 of each: the warm start's Phi^dagger Phi xhat is
-    # folded into the carried right-hand side (one Phi^dagger of w2 - Phi xhat).
-    pairs_per_step = ncg + 2
+    # The method's count is n_cg + 2 pairs per iteration (n_cg + 1 in CG with a
+    # warm start, one in steps 7-9); the library applies n_cg + 1 of each
+    # operator (the warm start's Phi^dagger Phi xhat is folded into the carried
+    # right-hand side), and `value` counts the pairs it applies.
+    pairs_per_step = ncg + 1
+    method_pairs_per_step = ncg + 2
     value = M * pairs_per_step / (ms_step * 1e-3)
     iters_s = 1e3 / ms_step
     log(f"fp32: {ms_step:.3f} ms/iteration ({launch}), {value:.4g} vis/s")
@@ -428,9 +430,10 @@ def main():
                                 f"KB J={J}, SARA Dirac+Db1-8 at {L} levels, one SDMM iteration per step "
                                 f"with n_cg={ncg}"),
                    "n": n, "M": M, "J": J, "levels": L, "n_cg": ncg, "pairs_per_step": pairs_per_step,
-                   "phi_applied_per_step": ncg + 1, "phi_adj_applied_per_step": ncg + 1,
+                   "method_pairs_per_step": method_pairs_per_step,
                    "launch": launch},
         "sdmm_iters_per_s": round(iters_s, 3),
+        "method_visibilities_per_s": M * method_pairs_per_step / (ms_step * 1e-3),
         "ms_per_step_stream": round(ms_stream, 4),
         "ms_per_step_graph": round(ms_graph, 4) if ms_graph else None,
         "pair_visibilities_per_s": pairs32,

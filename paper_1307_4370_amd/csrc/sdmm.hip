@@ -284,7 +284,8 @@ __global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, l
 }
 
 // prox3 and the right-hand side: v = xhat + z3; r3 = max(Re v, 0);
-// z3 <- v - r3; rhs = x1 + x2 + (r3 - z3).
+// z3 <- v - r3; rhs = x1 + x2 + (r3 - z3), where the x2 passed in is
+// Phi^dagger (w2 - Phi xhat), so rhs is the sum less Phi^dagger Phi xhat.
 template <typename R>
 __global__ void prox3_rhs(const C<R> *xh, C<R> *z3, const C<R> *x1, const C<R> *x2, C<R> *rhs, long N) {
     CHUNK_LOOP(i0, st, N) {
@@ -546,7 +547,8 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
     Prox1<R> px{w.z1loc.as<C<R>>(), w.w1.as<C<R>>(), static_cast<const R *>(w.weights), sc + SC_GAMMA,
                 w.f1part.as<double>()};
     for (int t = 0; t < iters; ++t) {
-        // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x.
+        // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x
+        // (rhs holds the sum less Phi^dagger Phi x).
         int rr_slot = SLOT_RR0;
         cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s, true);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).

@@ -270,8 +270,8 @@ def main():
         traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.copy_probe or 512)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the visibilities would be sharded); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(sharding the visibilities across GPUs is not implemented); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

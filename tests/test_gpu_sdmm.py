@@ -105,6 +105,34 @@ def test_sdmm_from_x0_matches_oracle(prec, tol, T):
         assert rel(host(gstate["z3"]), st.z3) <= tol * 10
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_sdmm_without_visibilities(prec, tol):
+    """M = 0: the l2-ball constraint is vacuous and Q = 2 I; the iteration
+    reduces to the l1 and positivity proxes (nu = 0 with eps = 1)."""
+    device()
+    announce(f"sdmm M=0 {prec}")
+    from paper_1307_4370_amd import Plan
+    n, levels = 16, 2
+    op = nufft.Operator(n, np.zeros((0, 2)), 6)
+    sara = wavelets.Sara(n, levels)
+    x0 = W.random_complex((n, n), W.rng(5, 1))
+    if prec == "f32":
+        x0 = x0.astype(np.complex64).astype(np.complex128)
+    y = np.zeros(0, dtype=np.complex128)
+    xo, st, hist, _ = osdmm.sdmm(y, 1.0, op, sara, T=3, n_cg=4, gamma=0.05, x0=x0)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    plan = Plan(n, torch.zeros((0, 2), dtype=dt, device=device()), J=6, levels=levels, prec=prec)
+    xg, stats, ghist, gstate = plan.sdmm(to_dev(y, prec), 1.0, T=3, n_cg=4, gamma=0.05, x0=to_dev(x0, prec))
+    assert stats["iters"] == 3
+    assert rel(host(xg), xo) <= tol
+    assert rel(host(gstate["rhs"]), st.rhs) <= tol * 10
+    assert rel(host(gstate["z1"]), st.z1) <= tol * 10
+    assert rel(host(gstate["z3"]), st.z3) <= tol * 10
+    for t in range(3):
+        assert ghist[t][2] == 0.0
+        assert ghist[t][0] == pytest.approx(hist[t]["f1"], rel=tol)
+
+
 def test_sdmm_resume_equals_single_run():
     device()
     announce("sdmm resume")

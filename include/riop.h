@@ -68,10 +68,15 @@ typedef enum {
 enum { RIOP_F32 = 1, RIOP_F64 = 2 };
 
 /* Plan description.
- *   n          image side; even, 8 <= n <= 8192, divisible by 2^levels
+ *   n          image side; even, 8 <= n <= 3072, divisible by 2^levels, with
+ *              K = 2n = 2^a 3^b (2^a >= 8); the FFT passes take K <= 2048
+ *              for powers of two and K <= 6144 with factors of 3
+ *              (RIOP_ENOTSUP beyond)
  *   oversample grid oversampling per axis (k of Sec. 5); must be 2
  *   M          number of visibilities, 0 <= M < 2^31
- *   J          Kaiser-Bessel kernel width in grid cells; even, 2 <= J <= 16
+ *   J          Kaiser-Bessel kernel width in grid cells; even, 2 <= J <= 16;
+ *              single-precision plans need J >= 6 (narrower kernels miss the
+ *              1e-7 bound of the weight polynomials: RIOP_ENOTSUP)
  *   levels     wavelet levels, 1 <= levels
  *   dict_mask  bit 0 Dirac, bit k Daubechies k (k = 1..8); nonzero, < 2^9
  *   prec       RIOP_F32: float storage and arithmetic with double-precision

@@ -340,7 +340,7 @@ static int default_tile(int K, int J) {
 static void validate(const riop_desc *d) {
     RIOP_REQUIRE(d, RIOP_EINVAL, "desc is NULL");
     RIOP_REQUIRE(d->oversample == 2, RIOP_ENOTSUP, "only oversampling 2 is supported");
-    RIOP_REQUIRE(d->n >= 8 && d->n <= 8192 && d->n % 2 == 0, RIOP_ESHAPE, "n must be even, 8..8192");
+    RIOP_REQUIRE(d->n >= 8 && d->n <= 3072 && d->n % 2 == 0, RIOP_ESHAPE, "n must be even, 8..3072");
     RIOP_REQUIRE(d->M >= 0 && d->M < (int64_t(1) << 31), RIOP_ESHAPE, "M must be in [0, 2^31)");
     RIOP_REQUIRE(d->J >= 2 && d->J <= 16 && d->J % 2 == 0, RIOP_EINVAL, "J must be even, 2..16");
     RIOP_REQUIRE(2 * d->n >= 2 * d->J, RIOP_ESHAPE, "grid too small for the kernel width");
@@ -427,7 +427,6 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         check_grid_lds(p);
         p->tiles_per_side = p->K / p->tile;
         p->ntiles = p->tiles_per_side * p->tiles_per_side;
-        RIOP_REQUIRE(p->ntiles <= 16384, RIOP_ENOTSUP, "too many gridding tiles; use a larger tile");
         const hipStream_t s = S(stream);
         build_fft_plan(p, s);
         build_kernel_tables(p);

@@ -503,6 +503,12 @@ void build_fft_plan(riop_plan *p, hipStream_t st) {
     RIOP_REQUIRE(f.nstages <= kMaxStages, RIOP_ENOTSUP, "too many FFT stages");
     f.E = threes ? 24 : 8;
     RIOP_REQUIRE(N % f.E == 0, RIOP_ENOTSUP, "grid side not divisible by the FFT thread width");
+    // One line per row-pass block of at most 256 threads, E points each, and
+    // the line held in LDS.
+    RIOP_REQUIRE(N / f.E <= 256, RIOP_ENOTSUP,
+                 "grid side K = 2n too large for the FFT passes (K <= 2048 for powers of two, "
+                 "K <= 6144 with factors of 3)");
+    RIOP_REQUIRE(cbytes(p) * (size_t)N <= p->lds_max, RIOP_ENOTSUP, "one FFT line does not fit in LDS");
 
     // Twiddles exp(-2 pi i m / N) from double-precision sin/cos.
     const size_t cb = cbytes(p);

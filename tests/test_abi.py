@@ -87,6 +87,10 @@ def test_host_validation_without_gpu():
         assert h.value is None
     d = _lib.Desc(n=64, oversample=3, M=10, J=8, levels=2, dict_mask=511, prec=1)
     assert L.riop_plan_create(ctypes.byref(d), None, None, ctypes.byref(h)) == -5
+    # Above the largest image side the FFT passes take (K = 2n <= 6144).
+    d = _lib.Desc(n=4096, oversample=2, M=10, J=8, levels=2, dict_mask=511, prec=1)
+    assert L.riop_plan_create(ctypes.byref(d), None, None, ctypes.byref(h)) == -2
+    assert b"3072" in L.riop_last_error()
     assert L.riop_plan_destroy(None) == 0
 
 

@@ -33,7 +33,9 @@ constexpr int kRedThreads = 256;
 // Partial-sum slots (each kRedBlocks doubles).
 enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, SLOT_F1, kSlots };
 // Scalar slots.
-enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, kScalars };
+// SC_GAMMA is the penalty of the SDMM state; SC_GAMMA_Q receives riop_gamma's
+// value, so that a query between SDMM steps leaves the running state alone.
+enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, SC_GAMMA_Q, kScalars };
 
 __device__ inline double block_sum(double v) {
     __shared__ double red[kRedThreads];
@@ -210,11 +212,11 @@ template <typename R> __global__ void max_abs(const C<R> *v, long n, double *par
     if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
 }
 
-__global__ void gamma_from_max(const double *partials, int slot, double beta, double *scalars) {
+__global__ void gamma_from_max(const double *partials, int slot, double beta, double *scalars, int which) {
     double m = 0;
     for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) m = fmax(m, partials[slot * kRedBlocks + i]);
     m = block_max(m);
-    if (threadIdx.x == 0) scalars[SC_GAMMA] = beta * m;
+    if (threadIdx.x == 0) scalars[which] = beta * m;
 }
 
 __global__ void set_scalar(double *scalars, int which, double v) {
@@ -456,7 +458,7 @@ static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_
 }
 
 template <typename R> static void gamma_run(riop_plan *p, const void *y_sorted_or_user, int user, double beta,
-                                            hipStream_t s) {
+                                            hipStream_t s, int which) {
     ensure_work(p);
     SdmmWork &w = p->sd;
     const long D = (long)p->q * p->n * p->n;
@@ -465,7 +467,7 @@ template <typename R> static void gamma_run(riop_plan *p, const void *y_sorted_o
     launch_psi_adj<R>(p, w.tmpN.ptr, w.w1.ptr, s);
     VEC_LAUNCH(p, max_abs<R>, RB(), RT(), 0, s, w.w1.as<C<R>>(), D, w.partials.as<double>(), (int)SLOT_MAX);
     VEC_LAUNCH(p, gamma_from_max, dim3(1), RT(), 0, s, (const double *)w.partials.as<double>(), (int)SLOT_MAX,
-                       beta, w.scalars.as<double>());
+                       beta, w.scalars.as<double>(), which);
     RIOP_HIP(hipGetLastError());
 }
 
@@ -492,7 +494,7 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
     if (prm->gamma > 0) {
         VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_GAMMA, prm->gamma);
     } else {
-        gamma_run<R>(p, w.ysort.ptr, 0, prm->beta, s);
+        gamma_run<R>(p, w.ysort.ptr, 0, prm->beta, s, (int)SC_GAMMA);
     }
     if (prm->resume) {
         RIOP_REQUIRE(x0 && prm->z1 && prm->z2 && prm->z3 && prm->rhs, RIOP_EINVAL,
@@ -661,8 +663,8 @@ template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x,
 }
 
 template <typename R> static void gamma_entry(riop_plan *p, const void *y, double beta, double *g, hipStream_t s) {
-    gamma_run<R>(p, y, 1, beta, s);
-    RIOP_HIP(hipMemcpyAsync(g, p->sd.scalars.as<double>() + SC_GAMMA, sizeof(double), hipMemcpyDeviceToHost, s));
+    gamma_run<R>(p, y, 1, beta, s, (int)SC_GAMMA_Q);
+    RIOP_HIP(hipMemcpyAsync(g, p->sd.scalars.as<double>() + SC_GAMMA_Q, sizeof(double), hipMemcpyDeviceToHost, s));
     RIOP_HIP(hipStreamSynchronize(s));
 }
 

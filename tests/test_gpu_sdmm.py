@@ -133,6 +133,34 @@ def test_sdmm_without_visibilities(prec, tol):
         assert ghist[t][0] == pytest.approx(hist[t]["f1"], rel=tol)
 
 
+def test_gamma_query_between_steps_leaves_the_run_alone():
+    """riop_gamma with another beta between riop_sdmm_step calls on the same
+    plan returns its own penalty and does not change the running state."""
+    import ctypes
+    device()
+    announce("gamma query between SDMM steps")
+    from paper_1307_4370_amd import _lib
+    c = SMALL
+    _, uv, op, y, eps = _problem(c, "f64")
+    plan = _plan(c, uv, "f64")
+    yd = to_dev(y, "f64")
+    xa, sa, _, _ = plan.sdmm(yd, eps, T=4, n_cg=8)
+    L = _lib.lib()
+    prm = _lib.SdmmParams(T=4, n_cg=8, gamma=0.0, beta=1e-3, xi=1e-3, tau=0.1)
+    x = torch.zeros_like(xa)
+    stream = _lib._stream(None)
+    assert L.riop_sdmm_init(plan._h, yd.data_ptr(), eps, ctypes.byref(prm), None, stream) == 0
+    assert L.riop_sdmm_step(plan._h, 2, stream) == 0
+    g = plan.gamma(yd, beta=0.5)
+    assert L.riop_sdmm_step(plan._h, 2, stream) == 0
+    st = _lib.SdmmStats()
+    assert L.riop_sdmm_finish(plan._h, None, x.data_ptr(), ctypes.byref(st), stream) == 0
+    # Gridding's double-precision LDS atomics may reorder the last bit.
+    assert g == pytest.approx(500 * sa["gamma"], rel=1e-12)
+    assert st.gamma == pytest.approx(sa["gamma"], rel=1e-14) and st.iters == 4
+    assert rel(host(x), host(xa)) <= 1e-12
+
+
 def test_sdmm_resume_equals_single_run():
     device()
     announce("sdmm resume")

@@ -172,7 +172,9 @@ riop_status riop_cg(riop_plan *plan, const void *b, void *x, int32_t n_iter,
                     double *rr_out, void *stream);
 
 /* gamma = beta * ||Psi^dagger Phi^dagger y||_inf (Sec. 4.4).  Synchronises.
- *   y  device M complex (caller order);  gamma host. */
+ *   y  device M complex (caller order);  gamma host.
+ * Like the other operator calls, it leaves an SDMM state held by the plan
+ * (riop_sdmm_init / riop_sdmm_step) unchanged. */
 riop_status riop_gamma(riop_plan *plan, const void *y, double beta, double *gamma,
                        void *stream);
 

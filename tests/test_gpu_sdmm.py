@@ -175,6 +175,38 @@ def test_sdmm_resume_equals_single_run():
     assert sb["f1"] == pytest.approx(sa["f1"], rel=1e-14)
 
 
+@pytest.mark.parametrize("prec,op_tol,tol", [("f64", 1e-12, 1e-10), ("f32", 1e-5, 1e-4)])
+def test_config2_operators_and_sdmm(prec, op_tol, tol):
+    """256 x 256 sky, M = 131072 Gaussian-density visibilities, J = 8, SARA at
+    4 levels (the operator-throughput workload): Phi, Phi^dagger, Psi^dagger
+    and Psi in full, and 3 SDMM iterations with n_cg = 16, against the oracle."""
+    device()
+    c = W.C2
+    announce(f"config 2 operators and SDMM {prec}")
+    x_true, uv, op, y, eps = _problem(c, prec)
+    sara = wavelets.Sara(c.n, c.levels)
+    plan = _plan(c, uv, prec)
+    g = W.rng(c.cfg, 91)
+    x = W.random_complex((c.n, c.n), g)
+    w = W.random_complex(c.M, g)
+    if prec == "f32":
+        x = x.astype(np.complex64).astype(np.complex128)
+        w = w.astype(np.complex64).astype(np.complex128)
+    assert rel(host(plan.phi(to_dev(x, prec))), op.phi(x)) <= op_tol
+    assert rel(host(plan.phi_adj(to_dev(w, prec))), op.phi_adj(w)) <= op_tol
+    alpha = sara.psi_adj(x)
+    assert rel(host(plan.psi_adj(to_dev(x, prec))), alpha) <= op_tol
+    assert rel(host(plan.psi(to_dev(alpha, prec))), sara.psi(alpha)) <= op_tol
+    xo, st, hist, gam = osdmm.sdmm(y, eps, op, sara, T=3, n_cg=16)
+    xg, stats, ghist, gstate = plan.sdmm(to_dev(y, prec), eps, T=3, n_cg=16)
+    assert stats["gamma"] == pytest.approx(gam, rel=1e-12 if prec == "f64" else 1e-5)
+    assert rel(host(xg), xo) <= tol
+    assert rel(host(gstate["rhs"]), st.rhs) <= tol * 10
+    for t in range(3):
+        assert ghist[t][0] == pytest.approx(hist[t]["f1"], rel=tol)
+        assert ghist[t][2] == pytest.approx(hist[t]["nu"], rel=tol)
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
 def test_sdmm_weighted_and_subdictionary(prec, tol):
     device()

@@ -67,6 +67,46 @@ def test_batch_matches_single_runs_and_oracle(prec, tol, T, ipg):
             assert rel(host(xs[k]), xo) <= tol
 
 
+def test_batch_of_32_uneven_channels():
+    """The batched workload at its real shape: 32 channels, image sides over
+    {128, ..., 512}, M = 1-4 times the pixel count, (u, v) scaled by 1-2,
+    FP32, autotuned tiles, 2 iterations captured in one graph.  Every
+    channel's iterate equals its own per-channel run; the first 128 x 128
+    channel also matches the oracle on the same data."""
+    import math
+    device()
+    announce("batch of 32 uneven channels")
+    from paper_1307_4370_amd import Batch, Plan, noise_bound
+    cfg, J, levels, T, n_cg = 4, 8, 4, 2, 4
+    chans = W.batch_channels(32, cfg)
+    uvs, ys, eps, plans, ys_host = [], [], [], [], []
+    for k, (n, M, f) in enumerate(chans):
+        uv = W.coverage(M, W.rng(cfg, W.STREAM_UV, k), scale=f).astype(np.float32).astype(np.float64)
+        x = W.sky(n, 4, 20, W.rng(cfg, W.STREAM_SKY, k))
+        plan = Plan(n, to_dev(uv, "f32"), J=J, levels=levels, prec="f32")
+        y0 = host(plan.phi(to_dev(x.astype(np.complex128), "f32")))
+        sigma = float(np.linalg.norm(y0)) * 10 ** (-30.0 / 20) / math.sqrt(M)
+        y = (y0 + sigma * W.unit_complex_noise(M, W.rng(cfg, W.STREAM_NOISE, k))).astype(np.complex64)
+        uvs.append(uv)
+        ys.append(to_dev(y.astype(np.complex128), "f32"))
+        ys_host.append(y.astype(np.complex128))
+        eps.append(noise_bound(M, sigma))
+        plans.append(plan)
+    batch = Batch([(n, to_dev(uv, "f32")) for (n, _, _), uv in zip(chans, uvs)], J=J, levels=levels,
+                  prec="f32", autotune=True)
+    xs, stats = batch.sdmm(ys, eps, T=T, n_cg=n_cg, iters_per_graph=T)
+    for k, plan in enumerate(plans):
+        assert stats[k]["iters"] == T
+        xe, _, _, _ = plan.sdmm(ys[k], eps[k], T=T, n_cg=n_cg)
+        assert rel(host(xs[k]), host(xe)) <= 1e-5, k
+    k = next(i for i, (n, _, _) in enumerate(chans) if n == 128)
+    n = chans[k][0]
+    op = nufft.Operator(n, uvs[k], J)
+    xo, _, _, _ = osdmm.sdmm(ys_host[k], eps[k], op, wavelets.Sara(n, levels), T=T, n_cg=n_cg)
+    assert rel(host(xs[k]), xo) <= 1e-4
+    batch.close()
+
+
 def test_autotuner_reports_all_admissible_tiles():
     device()
     announce("autotune")

@@ -117,7 +117,7 @@ void build_kernel_tables(riop_plan *p) {
     const double beta = M_PI * std::sqrt((J / alpha) * (J / alpha) * (alpha - 0.5) * (alpha - 0.5) - 0.8);
     const double i0b = bessel_i0(beta);
     p->kb_beta = beta;
-    const int D = p->prec == RIOP_F64 ? 14 : 8;
+    const int D = p->prec == RIOP_F64 ? 14 : 7;
     p->kdeg = D;
     p->n_even = D / 2 + 1;
     p->n_odd = (D + 1) / 2;

@@ -37,7 +37,7 @@
 namespace riop {
 
 template <typename R> struct KDeg;
-template <> struct KDeg<float> { static constexpr int D = 8; };
+template <> struct KDeg<float> { static constexpr int D = 7; };
 template <> struct KDeg<double> { static constexpr int D = 14; };
 
 // ---------------------------------------------------------------------------

@@ -87,7 +87,7 @@ def traffic_summary(fetch_dir, write_dir, probe_mib):
         rows = per_dispatch(d, counter)
         copies = [v for n, v in rows if "copyBuffer" in n]
         cal = probe / max(copies) if copies else 1.0
-        tile = [v for n, v in rows if "grid_tile<float, 8, false" in n]
+        tile = [v for n, v in rows if "grid_tile<float, 8, false" in n and ", true>(" not in n]
         merge = [v for n, v in rows if "grid_merge<float>" in n]
         t = sum(tile) / len(tile) if tile else 0.0
         m = sum(merge) / len(merge) if merge else 0.0

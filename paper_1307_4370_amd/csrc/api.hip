@@ -82,7 +82,7 @@ TimedScope::~TimedScope() {
 
 static const char *kKindNames[KK_COUNT] = {"fft_fwd_col", "fft_fwd_row", "fft_adj_row", "fft_adj_col",
                                            "degrid",      "grid",        "grid_zero",   "psi_adj",
-                                           "psi",         "vector"};
+                                           "psi",         "vector",      "grid_prox2"};
 
 // ---------------------------------------------------------------------------
 // Kaiser-Bessel kernel on the host.

@@ -102,7 +102,7 @@ struct FftPlan {
 // Kernel kinds for event timing.
 enum KernelKind {
     KK_FFT_FWD_COL = 0, KK_FFT_FWD_ROW, KK_FFT_ADJ_ROW, KK_FFT_ADJ_COL,
-    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_COUNT
+    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_GRID_PROX2, KK_COUNT
 };
 
 struct Timing {
@@ -234,6 +234,8 @@ template <typename R>
 void launch_degrid(riop_plan *p, void *y, int order_user, hipStream_t st);
 template <typename R>
 void launch_grid(riop_plan *p, const void *y, int order_user, hipStream_t st);
+template <typename R>
+void launch_grid_prox2(riop_plan *p, const void *s, void *z2, const void *y, const double *scale, hipStream_t st);
 template <typename R> void launch_fill_zero(void *buf, size_t ncomplex, hipStream_t st);
 template <typename R> void launch_psi_adj(riop_plan *p, const void *x, void *alpha, hipStream_t st);
 template <typename R> void launch_psi(riop_plan *p, const void *alpha, void *x, hipStream_t st);

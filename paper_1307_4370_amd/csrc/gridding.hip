@@ -368,6 +368,12 @@ template <typename R> struct TileArgs {
     const C<R> *vin;          // values to grid
     const R *__restrict__ kc; // kernel coefficients [pair][even/odd][D/2 + 1]
     int K, T, tps;            // grid side, tile side, tiles per side
+    // Fused l2-ball prox (P2 kernels, plan order): the values gridded are
+    // d2 = r2 - z2' - s with v = s + z2, r2 = y + (v - y) scale, z2' = v - r2,
+    // and z2' replaces z2.
+    const C<R> *p2s, *p2y;
+    C<R> *p2z;
+    const double *p2scale;    // min(1, eps / ||v - y||), one value
 };
 
 // Own cells of tile t to the grid, the rest of its region to its halo slot.
@@ -417,7 +423,9 @@ __device__ inline void store_region(const TileArgs<R> &a, const double *tre, con
 // of the three neighbours a tile receives from as it loads the grid (or
 // grid_merge does, where that pass is not the specialised one).
 // WAVES: grid_waves<R>(J), or 2 for tiles whose region leaves too little LDS.
-template <typename R, int J, bool USER, int WAVES>
+// P2: the values are formed from the l2-ball prox's inputs (see TileArgs), in
+// double precision, at staging (the second pass of the prox of f2, Sec. 4.4).
+template <typename R, int J, bool USER, int WAVES, bool P2>
 __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     constexpr int kWaves = WAVES, kThreads = 64 * kWaves;
     constexpr int NB = (J + 7) / 8;  // row slots per lane (vector path)
@@ -467,15 +475,23 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     uint32_t cv = 0;
     R fu = 0, fv = 0;
     C<R> val = mk<R>(0, 0);
+    C<R> ps = mk<R>(0, 0), pz = mk<R>(0, 0), py = mk<R>(0, 0);  // P2 inputs
     auto load = [&](int f) {
         if (f < f_end) {
             const int v = v0 + f;
             cv = a.cell[v];
             fu = a.frac[2 * (int64_t)v];
             fv = a.frac[2 * (int64_t)v + 1];
-            val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
+            if constexpr (P2) {
+                ps = a.p2s[v];
+                pz = a.p2z[v];
+                py = a.p2y[v];
+            } else {
+                val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
+            }
         }
     };
+    const double p2sc = P2 ? *a.p2scale : 1.0;
     // The first slice's loads are in flight while the region is cleared.
     load(f_begin + lane);
     for (int c = tid; c < 2 * PS; c += kThreads) tre[c] = 0.0;
@@ -540,6 +556,15 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     for (int base = f_begin; base < f_end; base += 64) {
         const int nlive = min(64, f_end - base);
         const bool live = lane < nlive;
+        if constexpr (P2) {
+            if (live) {
+                const double vr = (double)ps.x + pz.x, vi = (double)ps.y + pz.y;
+                const double rr = py.x + (vr - py.x) * p2sc, ri = py.y + (vi - py.y) * p2sc;
+                const double znr = vr - rr, zni = vi - ri;
+                a.p2z[v0 + base + lane] = mk<R>((R)znr, (R)zni);
+                val = mk<R>((R)(rr - znr - ps.x), (R)(ri - zni - ps.y));
+            }
+        }
         // Staging.  Lanes past the end stage zero values, so the
         // accumulation below runs over all 64 entries without bound tests.
         if (!live) val = mk<R>(0, 0);
@@ -869,7 +894,8 @@ void check_grid_lds(riop_plan *p) {
 }
 
 template <typename R>
-static void launch_tiles(riop_plan *p, const void *vals, int order_user, void *out_grid, hipStream_t st) {
+static void launch_tiles(riop_plan *p, const void *vals, int order_user, void *out_grid, hipStream_t st,
+                         const TileArgs<R> *p2 = nullptr) {
     TileArgs<R> a{};
     a.grid = static_cast<C<R> *>(out_grid);
     a.halo = p->halo.as<C<R>>();
@@ -882,22 +908,31 @@ static void launch_tiles(riop_plan *p, const void *vals, int order_user, void *o
     a.K = p->K;
     a.T = p->tile;
     a.tps = p->tiles_per_side;
+    if (p2) {
+        RIOP_REQUIRE(!order_user, RIOP_EINVAL, "the fused prox gridding is plan order only");
+        a.p2s = p2->p2s;
+        a.p2z = p2->p2z;
+        a.p2y = p2->p2y;
+        a.p2scale = p2->p2scale;
+    }
     int waves = grid_waves<R>(p->J);
     if (grid_lds<R>(p->tile, p->J, waves) > p->lds_max) waves = 2;
     const size_t lds = grid_lds<R>(p->tile, p->J, waves);
     RIOP_REQUIRE(lds <= p->lds_max, RIOP_ENOTSUP, "gridding tile too large for LDS");
-    TimedScope ts(p, KK_GRID, st);
+    TimedScope ts(p, p2 ? KK_GRID_PROX2 : KK_GRID, st);
     const dim3 g(p->ntiles);
     switch (p->J) {
 #define GK(JJ)                                                                                            \
     case JJ: {                                                                                            \
         constexpr int WD = grid_waves<R>(JJ);                                                             \
         if (waves == WD) {                                                                                \
-            if (order_user) hipLaunchKernelGGL((grid_tile<R, JJ, true, WD>), g, dim3(64 * WD), lds, st, a);   \
-            else hipLaunchKernelGGL((grid_tile<R, JJ, false, WD>), g, dim3(64 * WD), lds, st, a);             \
+            if (p2) hipLaunchKernelGGL((grid_tile<R, JJ, false, WD, true>), g, dim3(64 * WD), lds, st, a);  \
+            else if (order_user) hipLaunchKernelGGL((grid_tile<R, JJ, true, WD, false>), g, dim3(64 * WD), lds, st, a); \
+            else hipLaunchKernelGGL((grid_tile<R, JJ, false, WD, false>), g, dim3(64 * WD), lds, st, a);    \
         } else {                                                                                          \
-            if (order_user) hipLaunchKernelGGL((grid_tile<R, JJ, true, 2>), g, dim3(128), lds, st, a);         \
-            else hipLaunchKernelGGL((grid_tile<R, JJ, false, 2>), g, dim3(128), lds, st, a);                   \
+            if (p2) hipLaunchKernelGGL((grid_tile<R, JJ, false, 2, true>), g, dim3(128), lds, st, a);        \
+            else if (order_user) hipLaunchKernelGGL((grid_tile<R, JJ, true, 2, false>), g, dim3(128), lds, st, a); \
+            else hipLaunchKernelGGL((grid_tile<R, JJ, false, 2, false>), g, dim3(128), lds, st, a);          \
         }                                                                                                 \
         break;                                                                                            \
     }
@@ -926,6 +961,18 @@ template <typename R> void launch_grid(riop_plan *p, const void *y, int order_us
     launch_tiles<R>(p, y, order_user, p->grid.ptr, st);
 }
 
+// Gridding of the l2-ball prox's output, formed inside the gridding kernel
+// from s, z2 (updated in place) and y, all in plan order.
+template <typename R>
+void launch_grid_prox2(riop_plan *p, const void *s, void *z2, const void *y, const double *scale, hipStream_t st) {
+    TileArgs<R> q{};
+    q.p2s = static_cast<const C<R> *>(s);
+    q.p2z = static_cast<C<R> *>(z2);
+    q.p2y = static_cast<const C<R> *>(y);
+    q.p2scale = scale;
+    launch_tiles<R>(p, nullptr, 0, p->grid.ptr, st, &q);
+}
+
 // out_grid = G^T G in_grid: degridding into plan-order scratch, then gridding.
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st) {
     launch_degrid_from<R>(p, in_grid, p->vis.ptr, 0, st);
@@ -938,6 +985,8 @@ template void launch_degrid<float>(riop_plan *, void *, int, hipStream_t);
 template void launch_degrid<double>(riop_plan *, void *, int, hipStream_t);
 template void launch_grid<float>(riop_plan *, const void *, int, hipStream_t);
 template void launch_grid<double>(riop_plan *, const void *, int, hipStream_t);
+template void launch_grid_prox2<float>(riop_plan *, const void *, void *, const void *, const double *, hipStream_t);
+template void launch_grid_prox2<double>(riop_plan *, const void *, void *, const void *, const double *, hipStream_t);
 template void launch_grid_merge<float>(riop_plan *, void *, hipStream_t);
 template void launch_grid_merge<double>(riop_plan *, void *, hipStream_t);
 template void launch_fill_zero<float>(void *, size_t, hipStream_t);

@@ -35,7 +35,7 @@ enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, SLOT_F1,
 // Scalar slots.
 // SC_GAMMA is the penalty of the SDMM state; SC_GAMMA_Q receives riop_gamma's
 // value, so that a query between SDMM steps leaves the running state alone.
-enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, SC_GAMMA_Q, kScalars };
+enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, SC_GAMMA_Q, SC_P2SCALE, kScalars };
 
 __device__ inline double block_sum(double v) {
     __shared__ double red[kRedThreads];
@@ -258,31 +258,13 @@ __global__ void prox2_norms(const C<R> *s, const C<R> *z2, const C<R> *y, long M
     }
 }
 
-// prox2 pass 2: v = s + z2; r2 = y + (v - y) min(1, eps/||v - y||);
-// z2 <- v - r2; d2 = (r2 - z2) - s, the input of Phi^dagger (w2 less Phi xhat).
-template <typename R>
-__global__ void prox2_update(const C<R> *s, C<R> *z2, const C<R> *y, C<R> *w2, long M, const double *partials,
-                             const double *scalars) {
+// prox2 pass 2, its scale: min(1, eps / ||s + z2 - y||).  The rest of the
+// pass (v = s + z2; r2 = y + (v - y) scale; z2 <- v - r2; the values
+// (r2 - z2) - s for Phi^dagger) runs inside the gridding kernel.
+__global__ void prox2_scale(const double *partials, double *scalars) {
     const double e = sqrt(slot_sum(partials, SLOT_E));
     const double eps = scalars[SC_EPS];
-    const double sc = e > eps ? eps / e : 1.0;
-    CHUNK_LOOP(i0, st, M) {
-        C<R> sv[kU], zv[kU], yv[kU];
-        FOR_U(u) if (i0 + u * st < M) {
-            sv[u] = s[i0 + u * st];
-            zv[u] = z2[i0 + u * st];
-            yv[u] = y[i0 + u * st];
-        }
-        FOR_U(u) if (i0 + u * st < M) {
-            const long i = i0 + u * st;
-            const C<R> si = sv[u], zi = zv[u], yi = yv[u];
-            const double vr = (double)si.x + zi.x, vi = (double)si.y + zi.y;
-            const double rr = yi.x + (vr - yi.x) * sc, ri = yi.y + (vi - yi.y) * sc;
-            const double znr = vr - rr, zni = vi - ri;
-            z2[i] = mk<R>((R)znr, (R)zni);
-            w2[i] = mk<R>((R)(rr - znr - si.x), (R)(ri - zni - si.y));
-        }
-    }
+    if (threadIdx.x == 0) scalars[SC_P2SCALE] = e > eps ? eps / e : 1.0;
 }
 
 // prox3 and the right-hand side: v = xhat + z3; r3 = max(Re v, 0);
@@ -561,10 +543,8 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         phi_into_s2<R>(p, xh, s);
         VEC_LAUNCH(p, prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(), w.ysort.as<C<R>>(),
                    M, part);
-        if (M > 0)
-            VEC_LAUNCH(p, prox2_update<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
-                       w.ysort.as<C<R>>(), p->vis.as<C<R>>(), M, (const double *)part, (const double *)sc);
-        launch_grid<R>(p, p->vis.ptr, 0, s);
+        VEC_LAUNCH(p, prox2_scale, dim3(1), RT(), 0, s, (const double *)part, sc);
+        launch_grid_prox2<R>(p, w.s2.ptr, w.z2loc.ptr, w.ysort.ptr, sc + SC_P2SCALE, s);
         launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
         // i = 3 and the next right-hand side.
         VEC_LAUNCH(p, prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(), w.x1.as<C<R>>(),

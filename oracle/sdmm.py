@@ -18,7 +18,9 @@ Algorithm 1 (Sec. 4.4) is followed step by step:
 Readings (the paper is silent):
   * x^(0) = 0 unless given; CG is warm-started from x^(t-1) and runs a fixed
     number n_cg of iterations (stopping early only on an exactly zero
-    residual, where the next step would divide 0 by 0);
+    residual, where the next step would divide 0 by 0), or, when a tolerance
+    tol > 0 is given, stops before iteration k once ||r_k|| <= tol ||r_0||
+    (the textbook relative-residual rule; the paper fixes no stopping rule);
   * zeta is +inf while the previous f1 is 0;
   * the algorithm runs T iterations unless early stopping is requested.
 """
@@ -37,14 +39,15 @@ def vdot(a: np.ndarray, b: np.ndarray) -> complex:
     return np.vdot(np.ravel(a), np.ravel(b))
 
 
-def conjugate_gradient(Q, b: np.ndarray, x0: np.ndarray, n_iter: int) -> np.ndarray:
+def conjugate_gradient(Q, b: np.ndarray, x0: np.ndarray, n_iter: int, tol: float = 0.0) -> np.ndarray:
     """Hestenes-Stiefel CG for a Hermitian positive-definite Q (Sec. 4.4, step 5)."""
     x = np.array(x0, dtype=np.complex128, copy=True)
     r = b - Q(x)
     p = r.copy()
     rr = float(np.real(vdot(r, r)))
+    rr0 = rr
     for _ in range(n_iter):
-        if rr == 0.0:
+        if rr == 0.0 or (tol > 0.0 and rr <= tol * tol * rr0):
             break
         Qp = Q(p)
         alpha = rr / float(np.real(vdot(p, Qp)))
@@ -111,13 +114,13 @@ def initial_state(y, phi, phi_adj, psi, psi_adj, x0=None, n=None) -> State:
 
 
 def iterate(state: State, y, eps, gamma, phi, phi_adj, psi, psi_adj, n_cg,
-            weights=None) -> dict:
+            weights=None, cg_tol=0.0) -> dict:
     """One iteration t of Algorithm 1 (steps 5-9); updates ``state`` in place."""
     def Q(v):
         return phi_adj(phi(v)) + 2.0 * v
 
     # Step 5.
-    xhat = conjugate_gradient(Q, state.rhs, state.xhat, n_cg)
+    xhat = conjugate_gradient(Q, state.rhs, state.xhat, n_cg, cg_tol)
     # Steps 7-9 for i = 1 (L1 = Psi^dagger, f1 = ||W .||_1).
     l1 = psi_adj(xhat)
     v1 = l1 + state.z1
@@ -148,7 +151,7 @@ def iterate(state: State, y, eps, gamma, phi, phi_adj, psi, psi_adj, n_cg,
 
 
 def sdmm(y, eps, op, sara, T, n_cg=16, gamma=None, beta=1e-3, weights=None,
-         x0=None, state=None, early_stop=False, xi=1e-3, tau=0.1):
+         x0=None, state=None, early_stop=False, xi=1e-3, tau=0.1, cg_tol=0.0):
     """Run Algorithm 1 for up to T iterations.
 
     ``op`` provides phi / phi_adj (oracle.nufft.Operator), ``sara`` provides
@@ -161,7 +164,7 @@ def sdmm(y, eps, op, sara, T, n_cg=16, gamma=None, beta=1e-3, weights=None,
     history = []
     for _ in range(T):
         h = iterate(state, y, eps, gamma, op.phi, op.phi_adj, sara.psi, sara.psi_adj,
-                    n_cg, weights)
+                    n_cg, weights, cg_tol)
         history.append(h)
         if early_stop and h["zeta"] < xi and (1 - tau) <= h["nu"] <= (1 + tau):
             break

@@ -158,3 +158,50 @@ def test_gram_spectrum_bounded():
     np.testing.assert_allclose(A, A.conj().T, atol=1e-13)
     ev = np.linalg.eigvalsh(A)
     assert ev.min() > -1e-12
+
+
+def _phi_with_beta(x, uv, J, b):
+    """The oracle's Phi (Sec. 5) with the Kaiser-Bessel shape parameter b."""
+    n = x.shape[0]
+    K = nufft.grid_side(n)
+    d = 1.0 / kb.phihat(nufft.offsets(n), J, K, b)
+    rows = np.mod(nufft.offsets(n), K)
+    xp = np.zeros((K, K), dtype=np.complex128)
+    xp[np.ix_(rows, rows)] = d[:, None] * d[None, :] * x
+    X = (np.fft.fft2(xp) / K).ravel()
+    g = np.asarray(uv) * (K / (2 * np.pi))
+    a = kb.window(g, J)[:, :, None] + np.arange(J)[None, None, :]
+    w = kb.phi(g[:, :, None] - a, J, b)
+    am = np.mod(a, K)
+    cols = (am[:, 0, :, None] * K + am[:, 1, None, :]).reshape(len(uv), -1)
+    vals = (w[:, 0, :, None] * w[:, 1, None, :]).reshape(len(uv), -1)
+    return np.sum(vals * X[cols], axis=1)
+
+
+@pytest.mark.parametrize("J", [6, 8])
+def test_kaiser_bessel_beta_minimises_the_error(J):
+    """The shape parameter rule is chosen to minimise the interpolation error
+    at oversampling 2: against the exact sum, the rule's beta is within 10 % of
+    the smallest error over a scan of beta, and the rule without its -0.8 term
+    is clearly worse (pins the constant, not just the NUFFT's overall accuracy)."""
+    n, M = 32, 400
+    x = W.random_complex((n, n), W.rng(7, 1))
+    uv = W.coverage(M, W.rng(7, 2))
+    ref = nufft.direct(x, uv)
+    err = lambda b: np.linalg.norm(_phi_with_beta(x, uv, J, b) - ref) / np.linalg.norm(ref)
+    b0 = kb.beta(J)
+    scan = [err(b) for b in np.linspace(0.7 * b0, 1.2 * b0, 51)]
+    assert err(b0) <= 1.1 * min(scan)
+    assert err(np.pi * J / 2 * 1.5) >= 1.4 * err(b0)
+
+
+def test_direct_points_is_the_direct_sum_of_a_sparse_image():
+    n, M = 16, 300
+    g = W.rng(8, 1)
+    pix = g.integers(0, n, size=(7, 2))
+    amps = g.uniform(0, 1, size=7) + 0.2j
+    x = np.zeros((n, n), dtype=np.complex128)
+    np.add.at(x, (pix[:, 0], pix[:, 1]), amps)
+    uv = W.coverage(M, W.rng(8, 2))
+    np.testing.assert_allclose(nufft.direct_points(pix, amps, uv, n, chunk=64), nufft.direct(x, uv),
+                               rtol=0, atol=1e-13)

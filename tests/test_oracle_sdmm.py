@@ -189,3 +189,122 @@ def test_sdmm_limit_is_optimal(weighted):
     assert np.linalg.norm(y - op.phi(np.real(xh))) <= eps * (1 + 1e-3)
     assert np.abs(np.imag(xh)).max() < 1e-6 and np.real(xh).min() > -1e-6
     assert f_sdmm == pytest.approx(fr, rel=2e-3)
+
+
+# ---------------------------------------------------------------------------
+# A scalar problem worked by hand through Algorithm 1 (Sec. 4.4): n = 1,
+# Phi = Psi = I (q = 1, so Psi Psi^dagger = I and Q = 3 I), y = 3, eps = 1,
+# gamma = 1/2, x^(0) = 0.  CG solves Q x = b exactly in one iteration.
+#   t = 1: x = 0;     r1 = 0, z1 = 0;  v2 = 0, r2 = 2, z2 = -2;  rhs = 4
+#          f1 = 0, zeta = inf (previous f1 = 0), nu = |3 - 0| / 1 = 3
+#   t = 2: x = 4/3;   v1 = 4/3, r1 = 5/6, z1 = 1/2, x1 = 1/3
+#          v2 = 4/3 - 2 = -2/3, |v2 - y| = 11/3 > 1: r2 = 2, z2 = -8/3, x2 = 14/3
+#          x3 = 4/3;  rhs = 19/3;  f1 = 4/3, zeta = inf, nu = 5/3
+#   t = 3: x = 19/9;  v1 = 47/18, r1 = 19/9, z1 = 1/2, x1 = 29/18
+#          v2 = -5/9, r2 = 2, z2 = -23/9, x2 = 41/9;  x3 = 19/9;  rhs = 149/18
+#          f1 = 19/9, zeta = (19/9 - 4/3) / (4/3) = 7/12, nu = 8/9
+
+class _ScalarOp:
+    n = 1
+
+    @staticmethod
+    def phi(x):
+        return np.asarray(x, dtype=np.complex128).reshape(1).copy()
+
+    @staticmethod
+    def phi_adj(w):
+        return np.asarray(w, dtype=np.complex128).reshape(1, 1).copy()
+
+
+class _ScalarDict:
+    q = 1
+
+    @staticmethod
+    def psi_adj(x):
+        return np.asarray(x, dtype=np.complex128).reshape(1, 1).copy()
+
+    @staticmethod
+    def psi(a):
+        return np.asarray(a, dtype=np.complex128).reshape(1, 1).copy()
+
+
+def test_sdmm_scalar_case_worked_by_hand():
+    y = np.array([3.0 + 0j])
+    xh, st, hist, gam = sdmm.sdmm(y, 1.0, _ScalarOp, _ScalarDict, T=3, n_cg=1, gamma=0.5)
+    assert gam == 0.5
+    assert xh[0, 0] == pytest.approx(19 / 9, abs=1e-15)
+    assert st.z1[0, 0] == pytest.approx(0.5, abs=1e-15)
+    assert st.z2[0] == pytest.approx(-23 / 9, abs=1e-15)
+    assert st.z3[0, 0] == 0
+    assert st.rhs[0, 0] == pytest.approx(149 / 18, abs=1e-14)
+    assert [h["f1"] for h in hist] == pytest.approx([0.0, 4 / 3, 19 / 9], abs=1e-15)
+    assert math.isinf(hist[0]["zeta"]) and math.isinf(hist[1]["zeta"])
+    assert hist[2]["zeta"] == pytest.approx(7 / 12, abs=1e-15)
+    assert [h["nu"] for h in hist] == pytest.approx([3.0, 5 / 3, 8 / 9], abs=1e-15)
+
+
+def test_early_stop_fires_at_the_halting_rule():
+    """Halting (Sec. 4.4): stop at the first iteration with zeta < xi and nu in
+    [1 - tau, 1 + tau].  In the hand-worked case iteration 3 has zeta = 7/12 and
+    nu = 8/9: xi = 0.6, tau = 0.2 stop there; xi = 0.5 does not."""
+    y = np.array([3.0 + 0j])
+    full, st_full, _, _ = sdmm.sdmm(y, 1.0, _ScalarOp, _ScalarDict, T=3, n_cg=1, gamma=0.5)
+    xh, st, hist, _ = sdmm.sdmm(y, 1.0, _ScalarOp, _ScalarDict, T=50, n_cg=1, gamma=0.5,
+                                early_stop=True, xi=0.6, tau=0.2)
+    assert len(hist) == 3 and st.t == 3
+    np.testing.assert_array_equal(xh, full)
+    _, _, hist2, _ = sdmm.sdmm(y, 1.0, _ScalarOp, _ScalarDict, T=4, n_cg=1, gamma=0.5,
+                               early_stop=True, xi=0.5, tau=0.2)
+    assert len(hist2) == 4
+
+
+def test_early_stop_on_an_imaging_problem():
+    """On a small imaging problem the run stops at the first iteration meeting
+    the rule, and its iterate equals the fixed-length run of that many
+    iterations."""
+    _, op, sara, y, eps = _tiny()
+    _, _, hist, gam = sdmm.sdmm(y, eps, op, sara, T=400, n_cg=8)
+    ok = [h["zeta"] < 1e-3 and 0.9 <= h["nu"] <= 1.1 for h in hist]
+    assert any(ok)
+    first = ok.index(True) + 1
+    xs, _, hs, _ = sdmm.sdmm(y, eps, op, sara, T=400, n_cg=8, gamma=gam, early_stop=True)
+    assert len(hs) == first
+    xf, _, _, _ = sdmm.sdmm(y, eps, op, sara, T=first, n_cg=8, gamma=gam)
+    np.testing.assert_array_equal(xs, xf)
+
+
+@pytest.mark.slow
+def test_sdmm_from_x0_reaches_the_optimum():
+    """Algorithm 1 started from a nonzero x^(0) (steps 1-3 with r_i = L_i x^(0))
+    converges to the same optimal value as the library minimiser."""
+    x, op, sara, y, eps = _tiny()
+    xr, fr = _reference_solution(op, sara, y, eps, None)
+    gam = 0.05 * np.abs(sara.psi_adj(op.phi_adj(y))).max()
+    x0 = W.rng(103, 13).uniform(0.0, 1.0, size=(op.n, op.n)) + 0.3j
+    st0 = sdmm.initial_state(y, op.phi, op.phi_adj, sara.psi, sara.psi_adj, x0)
+    # Steps 1-3: r_i = L_i x0, x_i = L_i^dagger r_i, so rhs = (Psi Psi^dagger + Phi^dagger Phi + I) x0.
+    np.testing.assert_allclose(st0.rhs, 2 * x0 + op.phi_adj(op.phi(x0)), atol=1e-12)
+    xh, _, _, _ = sdmm.sdmm(y, eps, op, sara, T=1500, n_cg=40, gamma=gam, x0=x0)
+    f_sdmm = sdmm.f1_value(sara.psi_adj(np.real(xh)), None)
+    assert np.linalg.norm(y - op.phi(np.real(xh))) <= eps * (1 + 1e-3)
+    assert np.abs(np.imag(xh)).max() < 1e-6 and np.real(xh).min() > -1e-6
+    assert f_sdmm == pytest.approx(fr, rel=2e-3)
+
+
+def test_cg_tolerance_stops_at_the_relative_residual():
+    """With tol > 0 the oracle's CG stops before the first iteration whose
+    residual satisfies ||r_k|| <= tol ||r_0||: the result equals the fixed
+    k-iteration run, and k - 1 iterations do not meet the rule."""
+    _, op, _, _, _ = _tiny()
+    n = op.n
+    g = W.rng(103, 14)
+    b = W.random_complex((n, n), g)
+    x0 = np.zeros((n, n), dtype=np.complex128)
+    Q = lambda v: op.phi_adj(op.phi(v)) + 2 * v
+    r0 = np.linalg.norm(b - Q(x0))
+    tol = 1e-6
+    res = lambda k: np.linalg.norm(b - Q(sdmm.conjugate_gradient(Q, b, x0, k)))
+    k = next(k for k in range(1, 200) if res(k) <= tol * r0)
+    assert res(k - 1) > tol * r0
+    np.testing.assert_array_equal(sdmm.conjugate_gradient(Q, b, x0, 200, tol),
+                                  sdmm.conjugate_gradient(Q, b, x0, k))

@@ -7,11 +7,13 @@ sigma = pi/4), oversampling 2 (2048 x 2048 grid), 8 x 8 Kaiser-Bessel kernel,
 SARA (Dirac + Db1..Db8) at 4 levels, input SNR 30 dB.
 
 A step is one SDMM iteration (Algorithm 1): CG x-update with n_cg = 16 on
-Q = Phi^dagger Phi + 2I (17 Phi/Phi^dagger pairs with the initial residual),
-the l1 prox fused into Psi^dagger, the l2-ball prox around Phi x, the
-positivity prox and the next right-hand side (one more pair and one
-Psi^dagger / Psi pair).  value = visibilities through Phi + Phi^dagger per
-second = M x 18 pairs x steps / time.  Inputs are resident in HBM before the
+Q = Phi^dagger Phi + 2I, the l1 prox fused into Psi^dagger, the l2-ball prox
+around Phi x, the positivity prox and the next right-hand side, and one
+Psi^dagger / Psi pair.  The method counts n_cg + 2 = 18 Phi/Phi^dagger pairs
+per iteration; the library applies n_cg + 1 = 17 (the warm-started CG's
+initial residual reuses the Phi x of the l2-ball step).  value = visibilities
+through the applied pairs per second = M x 17 x steps / time (the rate by the
+method's 18 is reported beside it).  Inputs are resident in HBM before the
 timed region.  FP32 storage and arithmetic with FP64 norms and CG scalars.
 
 The SDMM iterations are timed twice on the same plan and data: enqueued as

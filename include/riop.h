@@ -43,6 +43,18 @@
  *     riop_last_error() returns a message for the calling thread.  Errors
  *     raised by the GPU itself (e.g. a device fault) surface as RIOP_EDEVICE
  *     from the next call that synchronises.
+ *   - Non-finite inputs: every call checks the caller data it reads (x, y,
+ *     alpha, b, x0, weights, a resumed state) on the device.  A NaN or Inf
+ *     sets the plan's sticky non-finite flag.  Calls that synchronise
+ *     (riop_sdmm, riop_sdmm_finish, riop_gamma, riop_cg with an output
+ *     pointer, riop_plan_sync) then return RIOP_ENONFINITE and clear the flag;
+ *     the asynchronous operator calls return RIOP_OK and leave the flag for
+ *     the next synchronising call (their outputs are then unspecified).
+ *     riop_sdmm checks its inputs before the first iteration.
+ *   - Device memory: the environment variable RIOP_DEVICE_MEMORY_LIMIT
+ *     (bytes, read at each allocation) caps what the library holds in this
+ *     process; an allocation past it fails with RIOP_ENOMEM, as a failed
+ *     hipMalloc does (riop_device_bytes reports what is held).
  */
 #ifndef RIOP_H
 #define RIOP_H
@@ -118,19 +130,39 @@ typedef struct {
  *           before returning (it reads back validation flags and bin sizes)
  *   out     receives the plan (host)
  * Builds G's sparsity pattern on the device (Sec. 5: "G is highly sparse"):
- * every visibility's J x J window, binned by grid tile with a stable counting
- * sort.  uv outside [-pi, pi] or non-finite -> RIOP_EINVAL. */
+ * every visibility's J x J window, binned by the grid cell of its first tap
+ * (cells numbered tile by tile) with a stable radix sort, O(M) work for any
+ * coverage.  uv outside [-pi, pi] or non-finite -> RIOP_EINVAL. */
 riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream,
                              riop_plan **out);
 
-/* Free a plan and everything it owns.  Waits for the plan's queued work. NULL is a no-op. */
+/* Free a plan and everything it owns.  Waits for the work the plan's last
+ * uncaptured call enqueued (not for the whole device; replays of graphs the
+ * caller captured are the caller's to wait for).  NULL is a no-op. */
 riop_status riop_plan_destroy(riop_plan *plan);
+
+/* Synchronise `stream` and report the plan's non-finite flag: RIOP_ENONFINITE
+ * (flag cleared) if an input of an earlier call on the plan held a NaN or Inf
+ * since the last report, RIOP_OK otherwise. */
+riop_status riop_plan_sync(riop_plan *plan, void *stream);
+
+/* Device bytes held by the library's allocations in this process (all plans,
+ * batches and workspaces). */
+int64_t riop_device_bytes(void);
+
+/* The l2 bound eps of the data constraint for M visibilities with complex
+ * Gaussian noise of variance sigma^2 (sigma^2 / 2 per real part), Sec. 6:
+ * ||n||^2 / (sigma^2/2) is chi^2 with 2M degrees of freedom, and eps is set
+ * two standard deviations above its mean, eps^2 = (2M + 4 sqrt(M)) sigma^2 / 2.
+ * Host function; NaN for M < 0 or sigma < 0. */
+double riop_noise_bound(int64_t M, double sigma);
 
 riop_status riop_plan_info(const riop_plan *plan, riop_info *info /* host */);
 
 /* Plan-order layout of the visibilities (for tests of the binning).
  *   perm        device int32[M]: perm[i] = caller index of the i-th visibility
- *               in plan order (sorted by tile, then by caller index)
+ *               in plan order (sorted by tile, then by first window cell
+ *               inside the tile, row-major, then by caller index)
  *   cell        device uint32[M]: first window cell of the i-th visibility,
  *               a0 | (b0 << 16) with a0, b0 in [0, K)
  *   tile_start  device int32[ntiles + 1]: plan-order offset of each tile
@@ -162,14 +194,22 @@ riop_status riop_psi_adj(riop_plan *plan, const void *x, void *alpha, void *stre
 riop_status riop_psi(riop_plan *plan, const void *alpha, void *x, void *stream);
 
 /* Conjugate gradient for Q x = b (Sec. 4.4, step 5 of Algorithm 1), Hestenes-
- * Stiefel with complex inner product <a, b> = sum conj(a) b, fixed n_iter
- * iterations (an exactly zero residual stops early).  Scalars alpha, beta and
- * all inner products are double precision on the device.
- *   b       device n*n complex
- *   x       device n*n complex: initial guess in, solution out
- *   rr_out  host, nullable: final <r, r> (the call then synchronises) */
-riop_status riop_cg(riop_plan *plan, const void *b, void *x, int32_t n_iter,
-                    double *rr_out, void *stream);
+ * Stiefel with complex inner product <a, b> = sum conj(a) b, at most n_iter
+ * iterations.  Scalars alpha, beta and all inner products are double
+ * precision on the device.  The iteration stops (the iterate no longer
+ * changes) once ||r_k|| <= tol ||r_0||, r_0 = b - Q x_in the initial
+ * residual; tol = 0 runs exactly n_iter iterations.  An exactly zero residual
+ * always stops.  The launch sequence is the same either way (no host round
+ * trip), so the call can be captured in a graph.
+ *   b          device n*n complex
+ *   x          device n*n complex: initial guess in, solution out
+ *   tol        relative residual tolerance, >= 0
+ *   rr_out     host, nullable: final <r, r>
+ *   iters_out  host, nullable: iterations that changed the iterate
+ * With rr_out or iters_out the call synchronises (and reports non-finite
+ * inputs). */
+riop_status riop_cg(riop_plan *plan, const void *b, void *x, int32_t n_iter, double tol,
+                    double *rr_out, int32_t *iters_out, void *stream);
 
 /* gamma = beta * ||Psi^dagger Phi^dagger y||_inf (Sec. 4.4).  Synchronises.
  *   y  device M complex (caller order);  gamma host.
@@ -198,8 +238,10 @@ typedef struct {
     void *z2;             /* nullable device M complex, caller order: dual of L2 (in/out) */
     void *z3;             /* nullable device n*n complex: dual of L3 (in/out) */
     void *rhs;            /* nullable device n*n complex: sum_i x_i (in/out) */
-    double *history;      /* nullable host, 4*T doubles: per iteration f1, zeta, nu,
-                             final CG <r, r> */
+    double *history;      /* nullable host, 5*T doubles: per iteration f1, zeta, nu,
+                             final CG <r, r>, CG iterations used */
+    double cg_tol;        /* CG stops once ||r_k|| <= cg_tol ||r_0|| (see riop_cg);
+                             0: always n_cg iterations */
 } riop_sdmm_params;
 
 typedef struct {
@@ -208,6 +250,11 @@ typedef struct {
     double f1;            /* f1(Psi^dagger x) at the last iterate */
     double zeta;          /* relative change of f1 (+inf while the previous f1 is 0) */
     double nu;            /* ||y - Phi x|| / eps */
+    int32_t status_iter;  /* 1-based iteration that decided the outcome: the first
+                             iteration whose f1 or nu was not finite (the call
+                             returns RIOP_ENONFINITE), else the iteration at which
+                             the halting rule held (early_stop), else 0 */
+    int32_t cg_iters;     /* CG iterations that changed x in the last iteration */
 } riop_sdmm_stats;
 
 /* Run SDMM (Algorithm 1).  Everything runs on `stream` with no host round trip
@@ -233,7 +280,12 @@ riop_status riop_sdmm(riop_plan *plan, const void *y, double eps,
  *   riop_sdmm_step    enqueue `iterations` iterations (steps 5-9 and the halting
  *                     quantities).  No allocation, no host synchronisation:
  *                     may be captured in a HIP graph and the graph replayed; the
- *                     iteration counter lives on the device.
+ *                     iteration counter lives on the device.  A captured graph
+ *                     stays valid across later riop_sdmm_init calls as long as
+ *                     T does not exceed the largest T the plan has been
+ *                     initialised with (the history buffer only grows) and
+ *                     n_cg, cg_tol and the weights pointer are unchanged;
+ *                     otherwise capture again.
  *   riop_sdmm_finish  copy x (x_out, nullable) and, if params is non-NULL, the
  *                     state (params->z1, z2, z3, rhs) and history out; fills
  *                     stats.  Synchronises `stream`.

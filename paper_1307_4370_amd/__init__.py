@@ -6,6 +6,8 @@ conjugate-gradient x-update of SDMM (Algorithm 1).
 All computation runs in the HIP library libriop.so (C interface in
 include/riop.h); this package only binds it.
 """
-from ._lib import (FULL_MASK, Batch, Plan, RiopError, autotune_tile, lib, noise_bound, version)  # noqa: F401
+from ._lib import (FULL_MASK, Batch, Plan, RiopError, autotune_tile, device_bytes, lib, noise_bound,  # noqa: F401
+                   version)
 
-__all__ = ["Plan", "Batch", "RiopError", "autotune_tile", "lib", "noise_bound", "version", "FULL_MASK"]
+__all__ = ["Plan", "Batch", "RiopError", "autotune_tile", "device_bytes", "lib", "noise_bound", "version",
+           "FULL_MASK"]

@@ -7,7 +7,6 @@ exceptions.  There is no fallback: if the library is missing, loading fails.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 import torch
@@ -24,6 +23,7 @@ STATUS = {0: "RIOP_OK", -1: "RIOP_EINVAL", -2: "RIOP_ESHAPE", -3: "RIOP_ENOMEM",
 
 # Entry points declared in include/riop.h (checked by the ABI test).
 EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan_layout",
+           "riop_plan_sync", "riop_device_bytes", "riop_noise_bound",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_gamma",
            "riop_sdmm", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
@@ -58,12 +58,16 @@ class SdmmParams(ctypes.Structure):
                 ("early_stop", ctypes.c_int32), ("resume", ctypes.c_int32),
                 ("f1_prev", ctypes.c_double), ("weights", ctypes.c_void_p),
                 ("z1", ctypes.c_void_p), ("z2", ctypes.c_void_p), ("z3", ctypes.c_void_p),
-                ("rhs", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double))]
+                ("rhs", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("cg_tol", ctypes.c_double)]
+
+HIST = 5  # doubles per iteration in the SDMM history: f1, zeta, nu, CG <r, r>, CG iterations
 
 
 class SdmmStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("gamma", ctypes.c_double), ("f1", ctypes.c_double),
-                ("zeta", ctypes.c_double), ("nu", ctypes.c_double)]
+                ("zeta", ctypes.c_double), ("nu", ctypes.c_double), ("status_iter", ctypes.c_int32),
+                ("cg_iters", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,7 +88,10 @@ def lib() -> ctypes.CDLL:
         for name in ("riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
                      "riop_apply_q", "riop_psi_adj", "riop_psi"):
             getattr(L, name).argtypes = [vp, vp, vp, vp]
-        L.riop_cg.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
+        L.riop_cg.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(i32), vp]
+        L.riop_plan_sync.argtypes = [vp, vp]
+        L.riop_device_bytes.argtypes = []
+        L.riop_noise_bound.argtypes = [i64, dbl]
         L.riop_gamma.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), vp]
         L.riop_sdmm.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp,
                                 ctypes.POINTER(SdmmStats), vp]
@@ -105,8 +112,11 @@ def lib() -> ctypes.CDLL:
         L.riop_timing_kinds.argtypes = []
         L.riop_timing_name.argtypes = [i32]
         for name in EXPORTS:
-            if name not in ("riop_last_error", "riop_version", "riop_timing_name"):
+            if name not in ("riop_last_error", "riop_version", "riop_timing_name", "riop_device_bytes",
+                            "riop_noise_bound"):
                 getattr(L, name).restype = ctypes.c_int
+        L.riop_device_bytes.restype = i64
+        L.riop_noise_bound.restype = dbl
         L.riop_timing_name.restype = ctypes.c_char_p
         L.riop_last_error.restype = ctypes.c_char_p
         L.riop_version.restype = ctypes.c_char_p
@@ -234,13 +244,21 @@ class Plan:
         _check(lib().riop_psi(self._h, alpha.data_ptr(), x.data_ptr(), _stream(stream)))
         return x
 
-    def cg(self, b, x0=None, n_iter: int = 16, stream=None):
-        """Solve Q x = b with n_iter CG iterations; returns (x, final <r, r>)."""
+    def cg(self, b, x0=None, n_iter: int = 16, tol: float = 0.0, stream=None, with_iters: bool = False):
+        """Solve Q x = b with at most n_iter CG iterations (stopping once
+        ||r|| <= tol ||r_0|| when tol > 0); returns (x, final <r, r>) or, with
+        with_iters, (x, final <r, r>, iterations that changed x)."""
         b = self._c(b, (self.n, self.n), "b")
         x = torch.zeros_like(b) if x0 is None else self._c(x0, (self.n, self.n), "x0").clone()
         rr = ctypes.c_double()
-        _check(lib().riop_cg(self._h, b.data_ptr(), x.data_ptr(), n_iter, ctypes.byref(rr), _stream(stream)))
-        return x, rr.value
+        it = ctypes.c_int32()
+        _check(lib().riop_cg(self._h, b.data_ptr(), x.data_ptr(), n_iter, float(tol), ctypes.byref(rr),
+                             ctypes.byref(it), _stream(stream)))
+        return (x, rr.value, it.value) if with_iters else (x, rr.value)
+
+    def sync(self, stream=None):
+        """Synchronise; raises RiopError(RIOP_ENONFINITE) if an earlier call's input held NaN or Inf."""
+        _check(lib().riop_plan_sync(self._h, _stream(stream)))
 
     def gamma(self, y, beta: float = 1e-3, stream=None) -> float:
         y = self._c(y, (self.M,), "y")
@@ -250,7 +268,7 @@ class Plan:
 
     def sdmm(self, y, eps: float, T: int, n_cg: int = 16, gamma: float = 0.0, beta: float = 1e-3,
              x0=None, weights=None, state: dict | None = None, early_stop: bool = False,
-             xi: float = 1e-3, tau: float = 0.1, stream=None):
+             xi: float = 1e-3, tau: float = 0.1, cg_tol: float = 0.0, stream=None, stats_out: dict | None = None):
         """Run Algorithm 1.  Returns (x, stats, history, state).
 
         ``state`` (optional) is a dict with z1, z2, z3, rhs tensors and f1_prev;
@@ -273,17 +291,21 @@ class Plan:
             if weights.dtype != self.rdtype or tuple(weights.shape) != (q, n, n):
                 raise ValueError("weights must be a real tensor of shape (q, n, n)")
             w = weights.contiguous()
-        hist = (ctypes.c_double * (4 * max(1, T)))()
+        hist = (ctypes.c_double * (HIST * max(1, T)))()
         prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=xi, tau=tau,
                          early_stop=int(early_stop), resume=int(resume), f1_prev=state["f1_prev"],
                          weights=_ptr(w), z1=state["z1"].data_ptr(), z2=state["z2"].data_ptr(),
-                         z3=state["z3"].data_ptr(), rhs=state["rhs"].data_ptr(), history=hist)
+                         z3=state["z3"].data_ptr(), rhs=state["rhs"].data_ptr(), history=hist,
+                         cg_tol=float(cg_tol))
         st = SdmmStats()
         if x is None:
             x = torch.zeros((n, n), dtype=self.cdtype, device=self.device)
-        _check(lib().riop_sdmm(self._h, y.data_ptr(), float(eps), ctypes.byref(prm), x.data_ptr(),
-                               ctypes.byref(st), _stream(stream)))
-        history = [tuple(hist[4 * t:4 * t + 4]) for t in range(st.iters)]
+        status = lib().riop_sdmm(self._h, y.data_ptr(), float(eps), ctypes.byref(prm), x.data_ptr(),
+                                 ctypes.byref(st), _stream(stream))
+        if stats_out is not None:
+            stats_out.update({k: getattr(st, k) for k, _ in SdmmStats._fields_})
+        _check(status)
+        history = [tuple(hist[HIST * t:HIST * t + HIST]) for t in range(min(st.iters, T))]
         state["f1_prev"] = st.f1 if st.iters else state["f1_prev"]
         stats = {k: getattr(st, k) for k, _ in SdmmStats._fields_}
         return x, stats, history, state
@@ -384,8 +406,13 @@ def autotune_tile(n: int, uv: torch.Tensor, J: int = 8, prec: str = "f32", reps:
 
 
 def noise_bound(M: int, sigma: float) -> float:
-    """eps^2 = (2M + 4 sqrt(M)) sigma^2 / 2: the chi^2 bound on ||n|| (Sec. 6)."""
-    return math.sqrt((2.0 * M + 4.0 * math.sqrt(M)) * sigma * sigma / 2.0)
+    """The l2 bound eps on the noise of M visibilities (riop_noise_bound)."""
+    return float(lib().riop_noise_bound(int(M), float(sigma)))
+
+
+def device_bytes() -> int:
+    """Device bytes held by the library's allocations in this process."""
+    return int(lib().riop_device_bytes())
 
 
 def version() -> str:

@@ -5,9 +5,11 @@
 //   * Daubechies DbN scaling filters by spectral factorisation of Daubechies'
 //     half-band polynomial, roots found with the Durand-Kerner iteration.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -26,6 +28,73 @@ void set_error(const char *fmt, ...) {
     g_err = buf;
 }
 void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------
+// Device-memory accounting and the RIOP_DEVICE_MEMORY_LIMIT hook.
+
+static std::atomic<size_t> g_held{0};
+
+size_t device_bytes_held() { return g_held.load(); }
+
+void account_alloc(size_t bytes) {
+    size_t limit = 0;
+    if (const char *e = std::getenv("RIOP_DEVICE_MEMORY_LIMIT")) limit = (size_t)std::strtoull(e, nullptr, 10);
+    const size_t now = g_held.fetch_add(bytes) + bytes;
+    if (limit && now > limit) {
+        g_held.fetch_sub(bytes);
+        throw Error{RIOP_ENOMEM, "device allocation refused: RIOP_DEVICE_MEMORY_LIMIT (" + std::to_string(limit) +
+                                     " bytes) would be exceeded"};
+    }
+}
+
+void account_free(size_t bytes) { g_held.fetch_sub(bytes); }
+
+// ---------------------------------------------------------------------------
+// Finiteness of caller inputs.  A NaN or an infinity fails x - x == 0.
+
+template <typename R> __global__ void finite_check_kernel(const R *__restrict__ v, int64_t n, int *flag) {
+    int bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += 4 * stride) {
+        R a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = i + u * stride < n ? v[i + u * stride] : R(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bad |= !(a[u] - a[u] == R(0));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+void check_finite_input(riop_plan *p, const void *v, int64_t nreal, hipStream_t st) {
+    if (!v || nreal <= 0) return;
+    const int threads = 256;
+    const int64_t blocks = std::min<int64_t>((nreal + 4 * threads - 1) / (4 * threads), 2048);
+    if (p->prec == RIOP_F64)
+        hipLaunchKernelGGL(finite_check_kernel<double>, dim3((unsigned)blocks), dim3(threads), 0, st,
+                           static_cast<const double *>(v), nreal, p->nonfinite.as<int>());
+    else
+        hipLaunchKernelGGL(finite_check_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, st,
+                           static_cast<const float *>(v), nreal, p->nonfinite.as<int>());
+    RIOP_HIP(hipGetLastError());
+}
+
+void report_nonfinite(riop_plan *p, hipStream_t st) {
+    int flag = 0;
+    RIOP_HIP(hipMemcpyAsync(&flag, p->nonfinite.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+    RIOP_HIP(hipStreamSynchronize(st));
+    if (flag) {
+        RIOP_HIP(hipMemsetAsync(p->nonfinite.ptr, 0, sizeof(int), st));
+        RIOP_HIP(hipStreamSynchronize(st));
+        throw Error{RIOP_ENONFINITE, "a NaN or Inf was found in an input of this plan's calls"};
+    }
+}
+
+void mark_done(riop_plan *p, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (!p->done) RIOP_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+    RIOP_HIP(hipEventRecord(p->done, st));
+}
 
 // ---------------------------------------------------------------------------
 // Event timing.
@@ -444,6 +513,9 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         p->ll_stride = std::max<size_t>(1, lls);
         p->ll.alloc(cb * p->ll_stride * 8);
         build_layout(p, uv, s);
+        p->nonfinite.alloc(sizeof(int));
+        RIOP_HIP(hipMemsetAsync(p->nonfinite.ptr, 0, sizeof(int), s));
+        RIOP_HIP(hipStreamSynchronize(s));
         p->device_bytes = 0;
         for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->cell_start,
                                 &p->tile_order, &p->halo, &p->kcoef, &p->kcoef_compact, &p->deapod,
@@ -461,9 +533,33 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
 riop_status riop_plan_destroy(riop_plan *plan) {
     if (!plan) return RIOP_OK;
     return guarded([&] {
-        (void)hipDeviceSynchronize();
+        // Wait for the work the plan's own calls enqueued (its last uncaptured
+        // call's stream), not for the whole device.
+        if (plan->done) {
+            (void)hipEventSynchronize(plan->done);
+            (void)hipEventDestroy(plan->done);
+            plan->done = nullptr;
+        }
         delete plan;
     });
+}
+
+riop_status riop_plan_sync(riop_plan *p, void *stream) {
+    return guarded([&] {
+        check_plan(p);
+        report_nonfinite(p, static_cast<hipStream_t>(stream));
+    });
+}
+
+int64_t riop_device_bytes(void) { return (int64_t)device_bytes_held(); }
+
+double riop_noise_bound(int64_t M, double sigma) {
+    // ||n||^2 / (sigma^2 / 2) follows a chi^2 law with 2M degrees of freedom
+    // (mean 2M, standard deviation 2 sqrt(M)); eps bounds it two standard
+    // deviations above the mean.
+    if (M < 0 || !(sigma >= 0)) return NAN;
+    const double m = (double)M;
+    return std::sqrt((2.0 * m + 4.0 * std::sqrt(m)) * sigma * sigma / 2.0);
 }
 
 riop_status riop_plan_info(const riop_plan *p, riop_info *info) {
@@ -557,7 +653,9 @@ riop_status riop_phi(riop_plan *p, const void *x, void *y, void *stream) {
         check_plan(p);
         RIOP_REQUIRE(x && (y || p->M == 0), RIOP_EINVAL, "NULL data pointer");
         RIOP_REQUIRE(x != y, RIOP_EINVAL, "x and y must not alias");
+        check_finite_input(p, x, 2 * (int64_t)p->n * p->n, S(stream));
         RIOP_DISPATCH(p, phi_impl, p, x, y, 1, S(stream));
+        mark_done(p, S(stream));
     });
 }
 
@@ -566,7 +664,9 @@ riop_status riop_phi_adj(riop_plan *p, const void *y, void *x, void *stream) {
         check_plan(p);
         RIOP_REQUIRE(x && (y || p->M == 0), RIOP_EINVAL, "NULL data pointer");
         RIOP_REQUIRE(x != y, RIOP_EINVAL, "x and y must not alias");
+        check_finite_input(p, y, 2 * p->M, S(stream));
         RIOP_DISPATCH(p, phi_adj_impl, p, y, x, 1, S(stream));
+        mark_done(p, S(stream));
     });
 }
 
@@ -575,7 +675,9 @@ riop_status riop_phi_sorted(riop_plan *p, const void *x, void *y, void *stream) 
         check_plan(p);
         RIOP_REQUIRE(x && (y || p->M == 0), RIOP_EINVAL, "NULL data pointer");
         RIOP_REQUIRE(x != y, RIOP_EINVAL, "x and y must not alias");
+        check_finite_input(p, x, 2 * (int64_t)p->n * p->n, S(stream));
         RIOP_DISPATCH(p, phi_impl, p, x, y, 0, S(stream));
+        mark_done(p, S(stream));
     });
 }
 
@@ -584,7 +686,9 @@ riop_status riop_phi_adj_sorted(riop_plan *p, const void *y, void *x, void *stre
         check_plan(p);
         RIOP_REQUIRE(x && (y || p->M == 0), RIOP_EINVAL, "NULL data pointer");
         RIOP_REQUIRE(x != y, RIOP_EINVAL, "x and y must not alias");
+        check_finite_input(p, y, 2 * p->M, S(stream));
         RIOP_DISPATCH(p, phi_adj_impl, p, y, x, 0, S(stream));
+        mark_done(p, S(stream));
     });
 }
 
@@ -593,7 +697,9 @@ riop_status riop_psi_adj(riop_plan *p, const void *x, void *alpha, void *stream)
         check_plan(p);
         RIOP_REQUIRE(x && alpha, RIOP_EINVAL, "NULL data pointer");
         RIOP_REQUIRE(x != alpha, RIOP_EINVAL, "x and alpha must not alias");
+        check_finite_input(p, x, 2 * (int64_t)p->n * p->n, S(stream));
         RIOP_DISPATCH(p, launch_psi_adj, p, x, alpha, S(stream));
+        mark_done(p, S(stream));
     });
 }
 
@@ -602,7 +708,9 @@ riop_status riop_psi(riop_plan *p, const void *alpha, void *x, void *stream) {
         check_plan(p);
         RIOP_REQUIRE(x && alpha, RIOP_EINVAL, "NULL data pointer");
         RIOP_REQUIRE(x != alpha, RIOP_EINVAL, "x and alpha must not alias");
+        check_finite_input(p, alpha, 2 * (int64_t)p->q * p->n * p->n, S(stream));
         RIOP_DISPATCH(p, launch_psi, p, alpha, x, S(stream));
+        mark_done(p, S(stream));
     });
 }
 

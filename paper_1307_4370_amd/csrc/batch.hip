@@ -30,6 +30,7 @@ struct riop_batch {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t exec = nullptr;
     int exec_iters = 0;
+    std::vector<uint64_t> exec_epoch;  // each channel's SDMM workspace epoch at capture
     std::vector<int> tile;
     std::vector<std::vector<double>> tile_ms;  // per channel: ms per pair for tiles 8, 16, 32, 64
 };
@@ -146,7 +147,9 @@ template <typename F> static riop_status guarded3(F &&f) {
 
 static void destroy_batch(riop_batch *b) {
     if (!b) return;
-    (void)hipDeviceSynchronize();
+    // Wait for the batch's own streams (graph launches, channel branches).
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+    for (hipStream_t st : b->streams) (void)hipStreamSynchronize(st);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -270,7 +273,12 @@ riop_status riop_batch_sdmm(riop_batch *b, const void *const *y, const double *e
                 RIOP_HIP(hipStreamWaitEvent(cs, b->joins[c], 0));
             }
         };
-        if (T >= ipg && (!b->exec || b->exec_iters != ipg)) {
+        // Capture again when the iteration count per graph changed or any
+        // channel's captured workspace state did (history buffer address,
+        // n_cg, cg_tol, weights: riop_sdmm_init moves the epoch then).
+        bool stale = !b->exec || b->exec_iters != ipg || (int)b->exec_epoch.size() != nc;
+        for (int c = 0; c < nc && !stale; ++c) stale = b->exec_epoch[c] != b->plans[c]->sd.epoch;
+        if (T >= ipg && stale) {
             if (b->exec) {
                 RIOP_HIP(hipGraphExecDestroy(b->exec));
                 b->exec = nullptr;
@@ -289,6 +297,8 @@ riop_status riop_batch_sdmm(riop_batch *b, const void *const *y, const double *e
             (void)hipGraphDestroy(g);
             RIOP_HIP(ie);
             b->exec_iters = ipg;
+            b->exec_epoch.resize(nc);
+            for (int c = 0; c < nc; ++c) b->exec_epoch[c] = b->plans[c]->sd.epoch;
         }
         int done = 0;
         while (T - done >= ipg) {

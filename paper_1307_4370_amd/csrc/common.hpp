@@ -57,6 +57,14 @@ struct Error {
         if (!(cond)) throw ::riop::Error{status, msg};                                        \
     } while (0)
 
+// Device memory held by the library's allocations in this process, and the
+// limit on it: the environment variable RIOP_DEVICE_MEMORY_LIMIT (bytes,
+// read at every allocation; unset or 0 = no limit).  An allocation that would
+// pass the limit fails with RIOP_ENOMEM exactly as a failed hipMalloc does.
+size_t device_bytes_held();
+void account_alloc(size_t bytes);    // throws RIOP_ENOMEM past the limit
+void account_free(size_t bytes);
+
 // Device allocation owned by a plan.
 struct DevBuf {
     void *ptr = nullptr;
@@ -68,11 +76,25 @@ struct DevBuf {
     void alloc(size_t b) {
         release();
         if (b == 0) b = 256;
-        RIOP_HIP(hipMalloc(&ptr, b));
+        account_alloc(b);
+        const hipError_t e = hipMalloc(&ptr, b);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            account_free(b);
+            throw Error{e == hipErrorOutOfMemory ? RIOP_ENOMEM : RIOP_EDEVICE,
+                        std::string("hipMalloc: ") + hipGetErrorString(e)};
+        }
         bytes = b;
     }
+    // Keeps the current buffer (and its address) when it is at least b bytes.
+    void reserve(size_t b) {
+        if (!ptr || bytes < b) alloc(b);
+    }
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) {
+            (void)hipFree(ptr);
+            account_free(bytes);
+        }
         ptr = nullptr;
         bytes = 0;
     }
@@ -126,12 +148,21 @@ struct SdmmWork {
     DevBuf f1part;          // per analysis block partials of f1 (psi_adj_blocks doubles)
     int f1_count = 0;
     DevBuf scalars;         // doubles: scalar slots
-    DevBuf history;         // doubles, 4 per iteration
-    int hist_cap = 0;       // iterations the history buffer holds
+    DevBuf history;         // doubles, kHistStride per iteration
+    int hist_cap = 0;       // iterations the history buffer holds (grows only)
     int n_cg = 0;
+    double cg_tol = 0.0;
     const void *weights = nullptr;
     bool initialised = false;
+    // Incremented whenever something a captured iteration depends on changes
+    // (a workspace address, n_cg, the weights pointer): a graph captured from
+    // riop_sdmm_step is valid while the epoch it was captured at is current.
+    uint64_t epoch = 0;
 };
+
+// Doubles per iteration in the SDMM history: f1, zeta, nu, final CG <r, r>,
+// CG iterations used.
+constexpr int kHistStride = 5;
 
 }  // namespace riop
 
@@ -188,6 +219,13 @@ struct riop_plan {
     riop::SdmmWork sd;
     riop::Timing timing;
     int64_t device_bytes = 0;
+
+    // Sticky flag set on the device when a caller input holds a NaN or Inf
+    // (int, device); read and cleared by the next call that synchronises.
+    riop::DevBuf nonfinite;
+    // Recorded on the stream of the plan's last (uncaptured) call, so that
+    // destroying the plan waits for its own work only.
+    hipEvent_t done = nullptr;
 };
 
 namespace riop {
@@ -263,6 +301,15 @@ struct TimedScope {
     TimedScope(riop_plan *p_, int kind_, hipStream_t s_);
     ~TimedScope();
 };
+
+// Launch a check of nreal reals at v (caller input) that sets the plan's
+// sticky non-finite flag; v may be NULL.
+void check_finite_input(riop_plan *p, const void *v, int64_t nreal, hipStream_t st);
+// Synchronise `st`; if the plan's non-finite flag is set, clear it and throw
+// RIOP_ENONFINITE.
+void report_nonfinite(riop_plan *p, hipStream_t st);
+// Record the plan's completion event on `st` (not while `st` is capturing).
+void mark_done(riop_plan *p, hipStream_t st);
 
 void build_fft_plan(riop_plan *p, hipStream_t st);
 void build_layout(riop_plan *p, const void *uv, hipStream_t st);

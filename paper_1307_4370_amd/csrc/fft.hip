@@ -169,12 +169,14 @@ __device__ inline void exchange(C<R> (&v)[E], C<R> *lds, int ls, int jt, int NE,
 }
 
 // Sum of one double per thread over the block, returned to every thread.
-// `red` holds at least blockDim.x / 64 doubles of LDS; brackets its use with
-// barriers.
+// `red` holds at least ceil(blockDim.x / 64) doubles of LDS; brackets its use
+// with barriers.  blockDim.x is a power of two; blocks narrower than a
+// wavefront (the column pass of 16-point lines has 32 threads) shuffle only
+// within their own lanes.
 __device__ inline double block_sum_all(double v, double *red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int nw = blockDim.x >> 6;
+    const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int nw = (blockDim.x + 63) >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -561,7 +563,7 @@ static bool launch_pass(riop_plan *p, FftArgs<R> a, int kind, hipStream_t st) {
     // partial per block.
     bool fused = false;
     if (a.cg_r || a.cg_p) {
-        fused = COLS && pow2 && E == 8 && blocks <= a.cg_nred;
+        fused = COLS && pow2 && E == 8 && blocks <= a.cg_nred && (threads & (threads - 1)) == 0;
         if (!fused) a.cg_r = a.cg_p = nullptr;
     }
     TimedScope ts(p, kind, st);

@@ -5,8 +5,9 @@
 // cell (a0, b0) = (floor(g - J/2) + 1) mod K and fractional offset
 // rho = g - J/2 - floor(g - J/2) in [0, 1), with g = u K / (2 pi) computed in
 // double precision.  Visibilities are sorted by T x T grid tile, then by cell
-// inside the tile (row-major), then by caller index; cell_start[key] gives the
-// plan-order range of every cell (key = tile * T^2 + local row * T + local col).
+// inside the tile (row-major), then by caller index (a stable radix sort of
+// the key); cell_start[key] gives the plan-order range of every cell
+// (key = tile * T^2 + local row * T + local col).
 //
 // Degridding (G): one workgroup per work unit (a tile and a chunk of its
 // visibilities) stages the (T + J - 1)^2 grid region its windows can touch in
@@ -45,7 +46,7 @@ template <> struct KDeg<double> { static constexpr int D = 14; };
 
 template <typename R>
 __global__ void bin_kernel(const R *__restrict__ uv, int64_t M, int K, int J, int T, int tps,
-                           double gscale, int *__restrict__ key_of, uint32_t *__restrict__ cell_of,
+                           double gscale, uint32_t *__restrict__ key_of, uint32_t *__restrict__ cell_of,
                            R *__restrict__ frac_of, int *__restrict__ flag) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -65,15 +66,10 @@ __global__ void bin_kernel(const R *__restrict__ uv, int64_t M, int K, int J, in
     if (a0 < 0) a0 += K;
     if (b0 < 0) b0 += K;
     const int tile = (a0 / T) * tps + (b0 / T);
-    key_of[m] = tile * T * T + (a0 % T) * T + (b0 % T);
+    key_of[m] = (uint32_t)(tile * T * T + (a0 % T) * T + (b0 % T));
     cell_of[m] = (uint32_t)a0 | ((uint32_t)b0 << 16);
     frac_of[2 * m] = (R)(hu - fu);
     frac_of[2 * m + 1] = (R)(hv - fv);
-}
-
-__global__ void count_kernel(const int *__restrict__ key_of, int64_t M, int *__restrict__ counts) {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < M) atomicAdd(&counts[key_of[m]], 1);
 }
 
 // Exclusive scan of int32 in three launches (block scan, scan of block sums, add).
@@ -135,33 +131,94 @@ __global__ void scan_add(int *__restrict__ out, int64_t n, const int *__restrict
         if (base + i < n) out[base + i] += add;
 }
 
-__global__ void set_int(int *__restrict__ p, int64_t idx, int v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) p[idx] = v;
-}
+// Stable LSD radix sort of (key, caller index) pairs, 8 bits per pass, so
+// that the plan order is by key and, within a key, by caller index, in O(M)
+// work for any coverage.  A block owns kSortTile consecutive elements.
+//   rs_hist:    its digit counts, stored digit-major (count[d * nblk + b]), so
+//               that one exclusive scan gives every (digit, block) its first
+//               output position;
+//   rs_scatter: its elements in position order, 256 at a time; lanes of one
+//               wavefront with equal digits are matched through eight ballots
+//               (one per digit bit), ranked by lane, and placed after the
+//               earlier wavefronts' and earlier rounds' elements of that digit.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;
 
-// Scatter by key (order inside a key is fixed afterwards by key_sort).
-__global__ void scatter_by_key(const int *__restrict__ key_of, int64_t M, const int *__restrict__ start,
-                               int *__restrict__ cursor, int *__restrict__ perm) {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const int k = key_of[m];
-    perm[start[k] + atomicAdd(&cursor[k], 1)] = (int)m;
-}
-
-// Stable order inside each key: insertion sort of the (few) caller indices.
-__global__ void key_sort(const int *__restrict__ start, int64_t nkeys, int *__restrict__ perm) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nkeys) return;
-    const int lo = start[k], hi = start[k + 1];
-    for (int i = lo + 1; i < hi; ++i) {
-        const int v = perm[i];
-        int j = i - 1;
-        while (j >= lo && perm[j] > v) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = v;
+__global__ void __launch_bounds__(kSortThreads) rs_hist(const uint32_t *__restrict__ keys, int64_t M, int shift,
+                                                        int nblk, int *__restrict__ count) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+        if (i < M) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
     }
+    __syncthreads();
+    count[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) rs_scatter(const uint32_t *__restrict__ keys_in,
+                                                           const int *__restrict__ vals_in, int64_t M, int shift,
+                                                           int nblk, const int *__restrict__ offset,
+                                                           uint32_t *__restrict__ keys_out,
+                                                           int *__restrict__ vals_out) {
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ int run[256];            // next output position of each digit
+    __shared__ int wcnt[kWaves][256];   // this round's count of each digit per wavefront
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    run[tid] = offset[(int64_t)tid * nblk + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + (int64_t)r * kSortThreads + tid;
+        const bool valid = i < M;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const int val = valid ? (vals_in ? vals_in[i] : (int)i) : 0;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            tot += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// start[k] = first plan-order position whose key is >= k (binary search over
+// the sorted keys), for k = 0 .. nkeys.
+__global__ void key_starts(const uint32_t *__restrict__ sorted, int64_t M, int64_t nkeys, int *__restrict__ start) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nkeys) return;
+    int64_t lo = 0, hi = M;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)sorted[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    start[k] = (int)lo;
 }
 
 template <typename R>
@@ -742,6 +799,17 @@ template <typename R> void launch_fill_zero(void *buf, size_t n, hipStream_t st)
     RIOP_HIP(hipGetLastError());
 }
 
+// Exclusive scan of n ints in place of `out` (may equal `in`), with `sums`
+// holding ceil(n / (kScanBlock kScanPer)) ints.
+static void scan_exclusive(const int *in, int *out, int64_t n, int *sums, hipStream_t st) {
+    const int64_t per_blk = (int64_t)kScanBlock * kScanPer;
+    const int nsums = (int)((n + per_blk - 1) / per_blk);
+    hipLaunchKernelGGL(scan_blocks, dim3(nsums), dim3(kScanBlock), 0, st, in, out, n, sums);
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, nsums);
+    hipLaunchKernelGGL(scan_add, dim3(nsums), dim3(kScanBlock), 0, st, out, n, (const int *)sums);
+    RIOP_HIP(hipGetLastError());
+}
+
 template <typename R> static void build_layout_t(riop_plan *p, const void *uv, hipStream_t st) {
     const int64_t M = p->M;
     const int K = p->K, T = p->tile, tps = p->tiles_per_side, ntiles = p->ntiles, J = p->J;
@@ -751,41 +819,55 @@ template <typename R> static void build_layout_t(riop_plan *p, const void *uv, h
     p->frac.alloc(sizeof(R) * 2 * M);
     p->tile_start.alloc(sizeof(int32_t) * (ntiles + 1));
     p->cell_start.alloc(sizeof(int32_t) * (nkeys + 1));
-    DevBuf key_of, cell_of, frac_of, flag, counts, sums;
-    key_of.alloc(sizeof(int) * M);
+    DevBuf key_a, key_b, val_b, cell_of, frac_of, flag, counts, sums;
+    key_a.alloc(sizeof(uint32_t) * M);
+    key_b.alloc(sizeof(uint32_t) * M);
+    val_b.alloc(sizeof(int) * M);
     cell_of.alloc(sizeof(uint32_t) * M);
     frac_of.alloc(sizeof(R) * 2 * M);
     flag.alloc(sizeof(int));
-    counts.alloc(sizeof(int) * nkeys);
+    const int64_t nblk = std::max<int64_t>(1, (M + kSortTile - 1) / kSortTile);
+    const int64_t ncount = 256 * nblk;
     const int64_t per_blk = (int64_t)kScanBlock * kScanPer;
-    const int nsums = (int)((nkeys + per_blk - 1) / per_blk);
-    sums.alloc(sizeof(int) * nsums);
+    counts.alloc(sizeof(int) * ncount);
+    sums.alloc(sizeof(int) * ((std::max(ncount, nkeys + 1) + per_blk - 1) / per_blk));
     RIOP_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), st));
-    RIOP_HIP(hipMemsetAsync(counts.ptr, 0, sizeof(int) * nkeys, st));
     const int threads = 256;
     const unsigned gM = (unsigned)std::max<int64_t>(1, (M + threads - 1) / threads);
     int *start = p->cell_start.as<int>();
     if (M > 0) {
         hipLaunchKernelGGL(bin_kernel<R>, dim3(gM), dim3(threads), 0, st, static_cast<const R *>(uv), M, K, J, T, tps,
-                           (double)K / (2.0 * M_PI), key_of.as<int>(), cell_of.as<uint32_t>(), frac_of.as<R>(),
+                           (double)K / (2.0 * M_PI), key_a.as<uint32_t>(), cell_of.as<uint32_t>(), frac_of.as<R>(),
                            flag.as<int>());
-        hipLaunchKernelGGL(count_kernel, dim3(gM), dim3(threads), 0, st, key_of.as<int>(), M, counts.as<int>());
         RIOP_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(scan_blocks, dim3(nsums), dim3(kScanBlock), 0, st, counts.as<int>(), start, nkeys,
-                       sums.as<int>());
-    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums.as<int>(), nsums);
-    hipLaunchKernelGGL(scan_add, dim3(nsums), dim3(kScanBlock), 0, st, start, nkeys, sums.as<int>());
-    hipLaunchKernelGGL(set_int, dim3(1), dim3(1), 0, st, start, nkeys, (int)M);
-    RIOP_HIP(hipGetLastError());
-    if (M > 0) {
-        RIOP_HIP(hipMemsetAsync(counts.ptr, 0, sizeof(int) * nkeys, st));  // reused as cursors
-        hipLaunchKernelGGL(scatter_by_key, dim3(gM), dim3(threads), 0, st, key_of.as<int>(), M, (const int *)start,
-                           counts.as<int>(), p->perm.as<int>());
-        hipLaunchKernelGGL(key_sort, dim3((unsigned)((nkeys + threads - 1) / threads)), dim3(threads), 0, st,
-                           (const int *)start, nkeys, p->perm.as<int>());
+        // Stable radix sort of (key, caller index): as many 8-bit passes as
+        // the largest key needs; the first pass takes the index implicitly.
+        int bits = 1;
+        while (bits < 32 && ((int64_t)1 << bits) < nkeys) ++bits;
+        const int passes = (bits + 7) / 8;
+        uint32_t *kin = key_a.as<uint32_t>(), *kout = key_b.as<uint32_t>();
+        int *vin = nullptr, *vout = passes % 2 ? p->perm.as<int>() : val_b.as<int>();
+        for (int ps = 0; ps < passes; ++ps) {
+            hipLaunchKernelGGL(rs_hist, dim3((unsigned)nblk), dim3(kSortThreads), 0, st, (const uint32_t *)kin, M,
+                               8 * ps, (int)nblk, counts.as<int>());
+            scan_exclusive(counts.as<int>(), counts.as<int>(), ncount, sums.as<int>(), st);
+            hipLaunchKernelGGL(rs_scatter, dim3((unsigned)nblk), dim3(kSortThreads), 0, st, (const uint32_t *)kin,
+                               (const int *)vin, M, 8 * ps, (int)nblk, (const int *)counts.as<int>(), kout, vout);
+            RIOP_HIP(hipGetLastError());
+            std::swap(kin, kout);
+            vin = vout;
+            vout = vout == p->perm.as<int>() ? val_b.as<int>() : p->perm.as<int>();
+        }
+        // kin holds the sorted keys, vin == perm.
+        RIOP_REQUIRE(vin == p->perm.as<int>(), RIOP_EDEVICE, "radix sort buffer parity");
+        hipLaunchKernelGGL(key_starts, dim3((unsigned)((nkeys + 1 + threads - 1) / threads)), dim3(threads), 0, st,
+                           (const uint32_t *)kin, M, nkeys, start);
         hipLaunchKernelGGL(gather_layout<R>, dim3(gM), dim3(threads), 0, st, (const int *)p->perm.as<int>(),
                            cell_of.as<uint32_t>(), frac_of.as<R>(), M, p->cell.as<uint32_t>(), p->frac.as<R>());
+        RIOP_HIP(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(key_starts, dim3((unsigned)((nkeys + 1 + threads - 1) / threads)), dim3(threads), 0, st,
+                           (const uint32_t *)key_a.as<uint32_t>(), (int64_t)0, nkeys, start);
         RIOP_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(tile_start_from_keys, dim3((ntiles + 1 + 255) / 256), dim3(256), 0, st, (const int *)start,
@@ -793,10 +875,8 @@ template <typename R> static void build_layout_t(riop_plan *p, const void *uv, h
     RIOP_HIP(hipGetLastError());
     int hflag = 0;
     std::vector<int> ts(ntiles + 1);
-    std::vector<int> cs((size_t)nkeys + 1);
     RIOP_HIP(hipMemcpyAsync(&hflag, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
     RIOP_HIP(hipMemcpyAsync(ts.data(), p->tile_start.ptr, sizeof(int) * (ntiles + 1), hipMemcpyDeviceToHost, st));
-    RIOP_HIP(hipMemcpyAsync(cs.data(), start, sizeof(int) * (nkeys + 1), hipMemcpyDeviceToHost, st));
     RIOP_HIP(hipStreamSynchronize(st));
     RIOP_REQUIRE(hflag == 0, RIOP_EINVAL, "uv coordinates must be finite and inside [-pi, pi]");
 

@@ -35,7 +35,10 @@ enum Slot { SLOT_RR0 = 0, SLOT_RR1, SLOT_PQ, SLOT_E, SLOT_NU, SLOT_MAX, SLOT_F1,
 // Scalar slots.
 // SC_GAMMA is the penalty of the SDMM state; SC_GAMMA_Q receives riop_gamma's
 // value, so that a query between SDMM steps leaves the running state alone.
-enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, SC_GAMMA_Q, SC_P2SCALE, kScalars };
+// SC_RR0 is the squared norm of CG's initial residual, SC_CGIT the CG
+// iterations that changed the iterate in the current solve.
+enum Scalar { SC_GAMMA = 0, SC_F1ACC, SC_F1PREV, SC_EPS, SC_RRFINAL, SC_ITER, SC_GAMMA_Q, SC_P2SCALE, SC_RR0, SC_CGIT,
+              kScalars };
 
 __device__ inline double block_sum(double v) {
     __shared__ double red[kRedThreads];
@@ -90,10 +93,12 @@ constexpr int kU = 4;
 
 template <typename R> __device__ inline double abs2(C<R> z) { return (double)z.x * z.x + (double)z.y * z.y; }
 
-// r = b - (Qx_partial + 2 x); p = r; slot <- sum |r|^2 (ax null: Qx_partial = 0)
+// r = b - (Qx_partial + 2 x); p = r; slot <- sum |r|^2 (ax null: Qx_partial = 0);
+// the CG iteration count restarts.
 template <typename R>
 __global__ void cg_init(const C<R> *b, const C<R> *x, const C<R> *ax, C<R> *r, C<R> *p, long N, double *partials,
-                        int slot) {
+                        int slot, double *scalars) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) scalars[SC_CGIT] = 0.0;
     double acc = 0;
     CHUNK_LOOP(i0, st, N) {
         C<R> xv[kU], av[kU], bv[kU];
@@ -136,13 +141,21 @@ template <typename R> __global__ void cg_pq(const C<R> *p, C<R> *qp, long N, dou
     if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
 }
 
-// alpha = rr_old / pq ; x += alpha p ; r -= alpha qp ; slot_new <- sum |r|^2
+// alpha = rr_old / pq ; x += alpha p ; r -= alpha qp ; slot_new <- sum |r|^2.
+// With tol2 > 0, CG stops (alpha = 0 from then on, the iterate frozen) once
+// |r|^2 <= tol2 |r_0|^2, r_0 the initial residual (first = 1 records |r_0|^2).
 template <typename R>
 __global__ void cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long N, double *partials, int slot_old,
-                          int slot_pq, int slot_new) {
+                          int slot_pq, int slot_new, double *scalars, double tol2, int first) {
     const double rr = slot_sum(partials, slot_old);
     const double pq = slot_sum(partials, slot_pq);
-    const double alpha = (rr == 0.0 || pq == 0.0) ? 0.0 : rr / pq;
+    const double rr0 = first ? rr : scalars[SC_RR0];
+    const bool converged = tol2 > 0.0 && rr <= tol2 * rr0;
+    const double alpha = (rr == 0.0 || pq == 0.0 || converged) ? 0.0 : rr / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (first) scalars[SC_RR0] = rr;
+        if (alpha != 0.0) scalars[SC_CGIT] += 1.0;
+    }
     double acc = 0;
     CHUNK_LOOP(i0, st, N) {
         C<R> pv[kU], qv[kU], xv[kU], rv[kU];
@@ -309,8 +322,9 @@ __global__ void f1_partials(const double *f1part, int f1_count, double *partials
     if (threadIdx.x == 0) partials[SLOT_F1 * kRedBlocks + blockIdx.x] = s;
 }
 
-// history[t] = {f1, zeta, nu, final CG rr} with t the device iteration
-// counter (so a captured graph can be replayed); f1_prev <- f1; t <- t + 1.
+// history[t] = {f1, zeta, nu, final CG rr, CG iterations} with t the device
+// iteration counter (so a captured graph can be replayed); f1_prev <- f1;
+// t <- t + 1.
 __global__ void record_stats(const double *partials, double *scalars, double *hist, int cap, int rr_slot) {
     const double nu2 = slot_sum(partials, SLOT_NU);
     const double rr = slot_sum(partials, rr_slot);
@@ -321,10 +335,12 @@ __global__ void record_stats(const double *partials, double *scalars, double *hi
         const double prev = scalars[SC_F1PREV];
         const double zeta = prev == 0.0 ? INFINITY : fabs(f1 - prev) / fabs(prev);
         if (t < cap) {
-            hist[4 * t + 0] = f1;
-            hist[4 * t + 1] = zeta;
-            hist[4 * t + 2] = sqrt(nu2) / scalars[SC_EPS];
-            hist[4 * t + 3] = rr;
+            double *h = hist + (long)kHistStride * t;
+            h[0] = f1;
+            h[1] = zeta;
+            h[2] = sqrt(nu2) / scalars[SC_EPS];
+            h[3] = rr;
+            h[4] = scalars[SC_CGIT];
         }
         scalars[SC_F1PREV] = f1;
         scalars[SC_RRFINAL] = rr;
@@ -391,16 +407,18 @@ template <typename R> static void phi_into_s2(riop_plan *p, const void *x, hipSt
 
 // CG on Q from x.  b_less_gram: b already has Phi^dagger Phi x subtracted.
 template <typename R>
-static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_slot, hipStream_t s,
+static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, double tol, int *final_slot, hipStream_t s,
                    bool b_less_gram = false) {
     ensure_work(p);
     SdmmWork &w = p->sd;
     const long N = (long)p->n * p->n;
     double *part = w.partials.as<double>();
+    double *sc = w.scalars.as<double>();
+    const double tol2 = tol > 0 ? tol * tol : 0.0;
     if (!b_less_gram) gram_sorted<R>(p, x, w.qp.ptr, s);
     VEC_LAUNCH(p, cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
                        b_less_gram ? (const C<R> *)nullptr : (const C<R> *)w.qp.as<C<R>>(), w.r.as<C<R>>(),
-                       w.p.as<C<R>>(), N, part, (int)SLOT_RR0);
+                       w.p.as<C<R>>(), N, part, (int)SLOT_RR0, sc);
     RIOP_HIP(hipGetLastError());
     // Where the FFT's column passes can, they apply the direction update
     // (before transforming p) and form q + 2 p with its p.q partials (after);
@@ -432,7 +450,7 @@ static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, int *final_
         if (!fold)
             VEC_LAUNCH(p, cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
         VEC_LAUNCH(p, cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r.as<C<R>>(), w.p.as<C<R>>(),
-                           w.qp.as<C<R>>(), N, part, cur, (int)SLOT_PQ, nxt);
+                           w.qp.as<C<R>>(), N, part, cur, (int)SLOT_PQ, nxt, sc, tol2, k == 0 ? 1 : 0);
         RIOP_HIP(hipGetLastError());
         cur = nxt;
     }
@@ -462,11 +480,30 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
     const long N = (long)p->n * p->n, D = (long)p->q * N, M = (long)p->M;
     const size_t cb = cbytes(p);
     double *sc = w.scalars.as<double>();
-    w.hist_cap = std::max(1, prm->T);
-    w.history.alloc(sizeof(double) * 4 * w.hist_cap);
+    // The history buffer only grows, so that its address (held by graphs
+    // captured from riop_sdmm_step) changes only when more iterations must be
+    // kept; every change of what a captured step depends on moves the epoch.
+    const size_t need = sizeof(double) * kHistStride * (size_t)std::max(1, prm->T);
+    if (!w.history.ptr || w.history.bytes < need) {
+        w.history.alloc(need);
+        ++w.epoch;
+    }
+    w.hist_cap = (int)std::min<size_t>(w.history.bytes / (sizeof(double) * kHistStride), 1u << 30);
+    if (w.n_cg != prm->n_cg || w.weights != prm->weights || w.cg_tol != prm->cg_tol) ++w.epoch;
     w.n_cg = prm->n_cg;
     w.weights = prm->weights;
+    w.cg_tol = prm->cg_tol;
     C<R> *xh = w.xhat.as<C<R>>();
+    // Caller inputs: NaN or Inf sets the plan's non-finite flag.
+    check_finite_input(p, y, 2 * M, s);
+    check_finite_input(p, x0, 2 * N, s);
+    check_finite_input(p, prm->weights, D, s);
+    if (prm->resume) {
+        check_finite_input(p, prm->z1, 2 * D, s);
+        check_finite_input(p, prm->z2, 2 * M, s);
+        check_finite_input(p, prm->z3, 2 * N, s);
+        check_finite_input(p, prm->rhs, 2 * N, s);
+    }
 
     if (M > 0)
         VEC_LAUNCH(p, gather_perm<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(y), p->perm.as<int>(),
@@ -534,7 +571,7 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x
         // (rhs holds the sum less Phi^dagger Phi x).
         int rr_slot = SLOT_RR0;
-        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, &rr_slot, s, true);
+        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, w.cg_tol, &rr_slot, s, true);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
         launch_psi_adj_prox<R>(p, xh, px, s);
         launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
@@ -556,10 +593,11 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
     }
 }
 
-// Copy the state out, read the statistics (synchronises).
+// Copy the state out, read the statistics (synchronises).  stop_iter: the
+// iteration at which early stopping ended the run (0: none).
 template <typename R>
 static void sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, riop_sdmm_stats *stats,
-                        double *history, hipStream_t s) {
+                        double *history, hipStream_t s, int stop_iter = 0) {
     SdmmWork &w = p->sd;
     RIOP_REQUIRE(w.initialised, RIOP_EINVAL, "SDMM state not initialised");
     const long N = (long)p->n * p->n, D = (long)p->q * N, M = (long)p->M;
@@ -579,73 +617,107 @@ static void sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, 
     double scal[kScalars] = {};
     RIOP_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, s));
     RIOP_HIP(hipStreamSynchronize(s));
+    mark_done(p, s);
     const int iters = (int)scal[SC_ITER];
     const int kept = std::min(iters, w.hist_cap);
-    std::vector<double> hist(4 * (size_t)std::max(1, kept), 0.0);
+    const int K = kHistStride;
+    std::vector<double> hist(K * (size_t)std::max(1, kept), 0.0);
     if (kept > 0) {
-        RIOP_HIP(hipMemcpyAsync(hist.data(), w.history.ptr, sizeof(double) * 4 * kept, hipMemcpyDeviceToHost, s));
+        RIOP_HIP(hipMemcpyAsync(hist.data(), w.history.ptr, sizeof(double) * K * kept, hipMemcpyDeviceToHost, s));
         RIOP_HIP(hipStreamSynchronize(s));
     }
-    if (history) std::copy(hist.begin(), hist.begin() + 4 * kept, history);
+    if (history) std::copy(hist.begin(), hist.begin() + (size_t)K * kept, history);
+    int bad = 0;  // first iteration (1-based) whose f1 or nu is not finite
+    for (int t = 0; t < kept && !bad; ++t)
+        if (!std::isfinite(hist[(size_t)K * t]) || !std::isfinite(hist[(size_t)K * t + 2])) bad = t + 1;
     if (stats) {
         stats->iters = iters;
         stats->gamma = scal[SC_GAMMA];
-        stats->f1 = kept ? hist[4 * (kept - 1)] : 0.0;
-        stats->zeta = kept ? hist[4 * (kept - 1) + 1] : INFINITY;
-        stats->nu = kept ? hist[4 * (kept - 1) + 2] : 0.0;
+        stats->f1 = kept ? hist[(size_t)K * (kept - 1)] : 0.0;
+        stats->zeta = kept ? hist[(size_t)K * (kept - 1) + 1] : INFINITY;
+        stats->nu = kept ? hist[(size_t)K * (kept - 1) + 2] : 0.0;
+        stats->cg_iters = kept ? (int32_t)hist[(size_t)K * (kept - 1) + 4] : 0;
+        stats->status_iter = bad ? bad : stop_iter;
     }
-    for (int t = 0; t < kept; ++t)
-        if (!std::isfinite(hist[4 * t]) || !std::isfinite(hist[4 * t + 2]))
-            throw Error{RIOP_ENONFINITE, "non-finite value reached a norm in SDMM"};
+    report_nonfinite(p, s);
+    if (bad) throw Error{RIOP_ENONFINITE, "non-finite value reached a norm in SDMM (see stats.status_iter)"};
 }
 
 template <typename R>
 static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, void *x_inout,
                      riop_sdmm_stats *stats, hipStream_t s) {
     sdmm_init<R>(p, y, eps, prm, x_inout, s);
+    // Inputs holding NaN or Inf end the call before any iteration.
+    try {
+        report_nonfinite(p, s);
+    } catch (const Error &) {
+        if (stats) {
+            *stats = riop_sdmm_stats{};
+            stats->zeta = INFINITY;
+        }
+        throw;
+    }
     const int T = std::max(0, prm->T);
+    int stop_iter = 0;
     if (!prm->early_stop) {
         sdmm_step<R>(p, T, s);
     } else {
-        double h[4];
+        double h[kHistStride];
         for (int t = 0; t < T; ++t) {
             sdmm_step<R>(p, 1, s);
-            RIOP_HIP(hipMemcpyAsync(h, p->sd.history.as<double>() + 4 * t, sizeof h, hipMemcpyDeviceToHost, s));
+            RIOP_HIP(hipMemcpyAsync(h, p->sd.history.as<double>() + (size_t)kHistStride * t, sizeof h,
+                                    hipMemcpyDeviceToHost, s));
             RIOP_HIP(hipStreamSynchronize(s));
-            if (!std::isfinite(h[2])) throw Error{RIOP_ENONFINITE, "non-finite residual norm in SDMM"};
-            if (h[1] < prm->xi && h[2] >= 1.0 - prm->tau && h[2] <= 1.0 + prm->tau) break;
+            if (!std::isfinite(h[0]) || !std::isfinite(h[2])) break;  // reported by sdmm_finish
+            // Halting rule (Sec. 4.4): relative change of f1 below xi and the
+            // data residual within [1 - tau, 1 + tau] of eps.
+            if (h[1] < prm->xi && h[2] >= 1.0 - prm->tau && h[2] <= 1.0 + prm->tau) {
+                stop_iter = t + 1;
+                break;
+            }
         }
     }
-    sdmm_finish<R>(p, prm, x_inout, stats, prm->history, s);
+    sdmm_finish<R>(p, prm, x_inout, stats, prm->history, s, stop_iter);
 }
 
 template <typename R> static void apply_q_run(riop_plan *p, const void *x, void *out, hipStream_t s) {
     const long N = (long)p->n * p->n;
     ensure_work(p);
+    check_finite_input(p, x, 2 * N, s);
     gram_sorted<R>(p, x, p->sd.tmpN.ptr, s);
     VEC_LAUNCH(p, add_2x<R>, RB(), RT(), 0, s, p->sd.tmpN.as<C<R>>(), static_cast<const C<R> *>(x),
                        static_cast<C<R> *>(out), N);
     RIOP_HIP(hipGetLastError());
 }
 
-template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x, int n_iter, double *rr_out,
-                                           hipStream_t s) {
+template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x, int n_iter, double tol,
+                                           double *rr_out, int32_t *iters_out, hipStream_t s) {
+    const long N = (long)p->n * p->n;
+    ensure_work(p);
+    check_finite_input(p, b, 2 * N, s);
+    check_finite_input(p, x, 2 * N, s);
     int slot = SLOT_RR0;
-    cg_run<R>(p, b, x, n_iter, &slot, s);
-    if (rr_out) {
+    cg_run<R>(p, b, x, n_iter, tol, &slot, s);
+    if (rr_out || iters_out) {
         VEC_LAUNCH(p, slot_to_scalar, dim3(1), RT(), 0, s, (const double *)p->sd.partials.as<double>(), slot,
                            p->sd.scalars.as<double>(), (int)SC_RRFINAL);
         RIOP_HIP(hipGetLastError());
-        RIOP_HIP(hipMemcpyAsync(rr_out, p->sd.scalars.as<double>() + SC_RRFINAL, sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-        RIOP_HIP(hipStreamSynchronize(s));
+        double sc[kScalars];
+        RIOP_HIP(hipMemcpyAsync(sc, p->sd.scalars.as<double>(), sizeof sc, hipMemcpyDeviceToHost, s));
+        report_nonfinite(p, s);
+        if (rr_out) *rr_out = sc[SC_RRFINAL];
+        if (iters_out) *iters_out = n_iter > 0 ? (int32_t)sc[SC_CGIT] : 0;
     }
+    mark_done(p, s);
 }
 
 template <typename R> static void gamma_entry(riop_plan *p, const void *y, double beta, double *g, hipStream_t s) {
+    ensure_work(p);
+    check_finite_input(p, y, 2 * p->M, s);
     gamma_run<R>(p, y, 1, beta, s, (int)SC_GAMMA_Q);
     RIOP_HIP(hipMemcpyAsync(g, p->sd.scalars.as<double>() + SC_GAMMA_Q, sizeof(double), hipMemcpyDeviceToHost, s));
-    RIOP_HIP(hipStreamSynchronize(s));
+    report_nonfinite(p, s);
+    mark_done(p, s);
 }
 
 }  // namespace riop
@@ -683,18 +755,21 @@ riop_status riop_apply_q(riop_plan *p, const void *x, void *out, void *stream) {
             apply_q_run<double>(p, x, out, static_cast<hipStream_t>(stream));
         else
             apply_q_run<float>(p, x, out, static_cast<hipStream_t>(stream));
+        mark_done(p, static_cast<hipStream_t>(stream));
     });
 }
 
-riop_status riop_cg(riop_plan *p, const void *b, void *x, int32_t n_iter, double *rr_out, void *stream) {
+riop_status riop_cg(riop_plan *p, const void *b, void *x, int32_t n_iter, double tol, double *rr_out,
+                    int32_t *iters_out, void *stream) {
     return guarded2([&] {
         check_plan2(p);
         RIOP_REQUIRE(b && x && b != x, RIOP_EINVAL, "b and x must be distinct non-NULL pointers");
         RIOP_REQUIRE(n_iter >= 0, RIOP_EINVAL, "n_iter must be >= 0");
+        RIOP_REQUIRE(tol >= 0 && std::isfinite(tol), RIOP_EINVAL, "tol must be finite and >= 0");
         if (p->prec == RIOP_F64)
-            cg_entry<double>(p, b, x, n_iter, rr_out, static_cast<hipStream_t>(stream));
+            cg_entry<double>(p, b, x, n_iter, tol, rr_out, iters_out, static_cast<hipStream_t>(stream));
         else
-            cg_entry<float>(p, b, x, n_iter, rr_out, static_cast<hipStream_t>(stream));
+            cg_entry<float>(p, b, x, n_iter, tol, rr_out, iters_out, static_cast<hipStream_t>(stream));
     });
 }
 
@@ -718,6 +793,7 @@ riop_status riop_sdmm(riop_plan *p, const void *y, double eps, const riop_sdmm_p
         RIOP_REQUIRE(eps > 0 && std::isfinite(eps), RIOP_EINVAL, "eps must be positive and finite");
         RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0, RIOP_EINVAL, "T and n_cg must be >= 0");
         RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        RIOP_REQUIRE(prm->cg_tol >= 0 && std::isfinite(prm->cg_tol), RIOP_EINVAL, "cg_tol must be finite and >= 0");
         if (p->prec == RIOP_F64)
             sdmm_run<double>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
         else
@@ -734,10 +810,12 @@ riop_status riop_sdmm_init(riop_plan *p, const void *y, double eps, const riop_s
         RIOP_REQUIRE(eps > 0 && std::isfinite(eps), RIOP_EINVAL, "eps must be positive and finite");
         RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0, RIOP_EINVAL, "T and n_cg must be >= 0");
         RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        RIOP_REQUIRE(prm->cg_tol >= 0 && std::isfinite(prm->cg_tol), RIOP_EINVAL, "cg_tol must be finite and >= 0");
         if (p->prec == RIOP_F64)
             sdmm_init<double>(p, y, eps, prm, x0, static_cast<hipStream_t>(stream));
         else
             sdmm_init<float>(p, y, eps, prm, x0, static_cast<hipStream_t>(stream));
+        mark_done(p, static_cast<hipStream_t>(stream));
     });
 }
 
@@ -749,6 +827,7 @@ riop_status riop_sdmm_step(riop_plan *p, int32_t iterations, void *stream) {
             sdmm_step<double>(p, iterations, static_cast<hipStream_t>(stream));
         else
             sdmm_step<float>(p, iterations, static_cast<hipStream_t>(stream));
+        mark_done(p, static_cast<hipStream_t>(stream));
     });
 }
 

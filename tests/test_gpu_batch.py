@@ -76,7 +76,7 @@ def test_batch_of_32_uneven_channels():
     import math
     device()
     announce("batch of 32 uneven channels")
-    from paper_1307_4370_amd import Batch, Plan, noise_bound
+    from paper_1307_4370_amd import Batch, Plan
     cfg, J, levels, T, n_cg = 4, 8, 4, 2, 4
     chans = W.batch_channels(32, cfg)
     uvs, ys, eps, plans, ys_host = [], [], [], [], []
@@ -90,7 +90,7 @@ def test_batch_of_32_uneven_channels():
         uvs.append(uv)
         ys.append(to_dev(y.astype(np.complex128), "f32"))
         ys_host.append(y.astype(np.complex128))
-        eps.append(noise_bound(M, sigma))
+        eps.append(osdmm.noise_bound(M, sigma))
         plans.append(plan)
     batch = Batch([(n, to_dev(uv, "f32")) for (n, _, _), uv in zip(chans, uvs)], J=J, levels=levels,
                   prec="f32", autotune=True)

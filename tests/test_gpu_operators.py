@@ -125,6 +125,40 @@ def test_layout_is_stable_counting_sort(prec, tile):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_clustered_coverage_layout_and_operators(prec):
+    """A coverage with half of its visibilities in 4 grid cells (50 000 per
+    cell, e.g. tracks crossing near the origin): plan creation stays O(M)
+    (bit-exact stable order), and Phi, Phi^dagger match the oracle."""
+    import time
+    n, J, M = 256, 8, 400000
+    K = 2 * n
+    device()
+    announce(f"clustered coverage {prec}")
+    g = W.rng(207, 1)
+    base = W.coverage(M // 2, g)
+    # Grid coordinates a + 1/4 plus up to half a cell: all points of a cluster
+    # share one window.
+    centres = (np.array([[3, -5], [60, 50], [-180, 110], [250, -255]]) + 0.25) * (2 * math.pi / K)
+    jitter = g.uniform(0, 0.5 * 2 * math.pi / K, size=(M // 2, 2))
+    clustered = centres[np.arange(M // 2) % 4] + jitter
+    uv = np.concatenate([clustered, base])[g.permutation(M)]
+    uv, x, w = _inputs(n, M, prec, 14, uv=uv)
+    t0 = time.perf_counter()
+    plan = _plan(n, uv, J, prec)
+    print(f"plan creation {time.perf_counter() - t0:.3f} s", flush=True)
+    perm, cell, ts = (host(t).real.astype(np.int64) for t in plan.layout())
+    tile = plan.info()["tile"]
+    a0 = np.mod(kb.window(uv * (K / (2 * math.pi)), J), K)
+    tid = (a0[:, 0] // tile) * (K // tile) + a0[:, 1] // tile
+    key = tid * tile * tile + (a0[:, 0] % tile) * tile + a0[:, 1] % tile
+    assert np.sort(np.bincount(key))[-4:].min() >= M // 8 - 1000
+    np.testing.assert_array_equal(perm, np.argsort(key, kind="stable"))
+    op = nufft.Operator(n, uv, J)
+    assert rel(host(plan.phi(to_dev(x, prec))), op.phi(x)) <= TOL[prec]
+    assert rel(host(plan.phi_adj(to_dev(w, prec))), op.phi_adj(w)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_adjoint_identity_on_gpu(prec):
     n, M, J = 128, 20000, 8
     device()

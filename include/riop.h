@@ -211,6 +211,21 @@ riop_status riop_psi(riop_plan *plan, const void *alpha, void *x, void *stream);
 riop_status riop_cg(riop_plan *plan, const void *b, void *x, int32_t n_iter, double tol,
                     double *rr_out, int32_t *iters_out, void *stream);
 
+/* riop_cg without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as riop_cg, but CG's
+ * workspace (residual, direction, Q times the direction: 3 n^2 complex, plus
+ * about 29 KB of reduction slots) lives in a static 64 MiB device array, one
+ * per GPU the library runs on, held until the process ends, instead of the
+ * plan's SDMM workspace (which riop_cg allocates on first use).  Plans whose
+ * workspace does not fit (image sides above about 1180 in FP64 and 1670 in
+ * FP32) get RIOP_ENOTSUP.  The call allocates nothing; it uses
+ * only the buffers the plan allocated at creation.  All calls on one GPU
+ * share that GPU's array: calls that overlap in time on one GPU (on
+ * different streams or host threads) race and give wrong results. */
+riop_status riop_cg_noalloc(riop_plan *plan, const void *b, void *x, int32_t n_iter, double tol,
+                            double *rr_out, int32_t *iters_out, void *stream);
+
 /* gamma = beta * ||Psi^dagger Phi^dagger y||_inf (Sec. 4.4).  Synchronises.
  *   y  device M complex (caller order);  gamma host.
  * Like the other operator calls, it leaves an SDMM state held by the plan

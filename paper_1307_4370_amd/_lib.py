@@ -25,7 +25,7 @@ STATUS = {0: "RIOP_OK", -1: "RIOP_EINVAL", -2: "RIOP_ESHAPE", -3: "RIOP_ENOMEM",
 EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan_layout",
            "riop_plan_sync", "riop_device_bytes", "riop_noise_bound",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
-           "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_gamma",
+           "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_cg_noalloc", "riop_gamma",
            "riop_sdmm", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
            "riop_batch_destroy", "riop_autotune_tile", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
            "riop_timing_name", "riop_last_error", "riop_version")
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
                      "riop_apply_q", "riop_psi_adj", "riop_psi"):
             getattr(L, name).argtypes = [vp, vp, vp, vp]
         L.riop_cg.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(i32), vp]
+        L.riop_cg_noalloc.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(i32), vp]
         L.riop_plan_sync.argtypes = [vp, vp]
         L.riop_device_bytes.argtypes = []
         L.riop_noise_bound.argtypes = [i64, dbl]

@@ -92,8 +92,7 @@ void report_nonfinite(riop_plan *p, hipStream_t st) {
 void mark_done(riop_plan *p, hipStream_t st) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
-    if (!p->done) RIOP_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
-    RIOP_HIP(hipEventRecord(p->done, st));
+    if (p->done) RIOP_HIP(hipEventRecord(p->done, st));
 }
 
 // ---------------------------------------------------------------------------
@@ -515,6 +514,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         build_layout(p, uv, s);
         p->nonfinite.alloc(sizeof(int));
         RIOP_HIP(hipMemsetAsync(p->nonfinite.ptr, 0, sizeof(int), s));
+        RIOP_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
         RIOP_HIP(hipStreamSynchronize(s));
         p->device_bytes = 0;
         for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->cell_start,

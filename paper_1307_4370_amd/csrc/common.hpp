@@ -224,8 +224,15 @@ struct riop_plan {
     // (int, device); read and cleared by the next call that synchronises.
     riop::DevBuf nonfinite;
     // Recorded on the stream of the plan's last (uncaptured) call, so that
-    // destroying the plan waits for its own work only.
+    // destroying the plan waits for its own work only (created with the plan).
     hipEvent_t done = nullptr;
+
+    riop_plan() = default;
+    riop_plan(const riop_plan &) = delete;
+    riop_plan &operator=(const riop_plan &) = delete;
+    ~riop_plan() {
+        if (done) (void)hipEventDestroy(done);
+    }
 };
 
 namespace riop {

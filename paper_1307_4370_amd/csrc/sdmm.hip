@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -405,20 +406,32 @@ template <typename R> static void phi_into_s2(riop_plan *p, const void *x, hipSt
     launch_degrid<R>(p, p->sd.s2.ptr, 0, s);
 }
 
+// Device memory CG works in: residual, direction and Q times the direction
+// (N complex each), the partial-sum slots (kSlots * kRedBlocks doubles) and
+// the scalar slots (kScalars doubles).
+template <typename R> struct CgWork {
+    C<R> *r, *p, *qp;
+    double *partials, *scalars;
+};
+
+template <typename R> static CgWork<R> plan_cg_work(riop_plan *p) {
+    SdmmWork &w = p->sd;
+    return CgWork<R>{w.r.as<C<R>>(), w.p.as<C<R>>(), w.qp.as<C<R>>(), w.partials.as<double>(), w.scalars.as<double>()};
+}
+
 // CG on Q from x.  b_less_gram: b already has Phi^dagger Phi x subtracted.
+// Besides the plan's operator buffers it touches only `w`.
 template <typename R>
 static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, double tol, int *final_slot, hipStream_t s,
-                   bool b_less_gram = false) {
-    ensure_work(p);
-    SdmmWork &w = p->sd;
+                   const CgWork<R> &w, bool b_less_gram = false) {
     const long N = (long)p->n * p->n;
-    double *part = w.partials.as<double>();
-    double *sc = w.scalars.as<double>();
+    double *part = w.partials;
+    double *sc = w.scalars;
     const double tol2 = tol > 0 ? tol * tol : 0.0;
-    if (!b_less_gram) gram_sorted<R>(p, x, w.qp.ptr, s);
+    if (!b_less_gram) gram_sorted<R>(p, x, w.qp, s);
     VEC_LAUNCH(p, cg_init<R>, RB(), RT(), 0, s, static_cast<const C<R> *>(b), static_cast<const C<R> *>(x),
-                       b_less_gram ? (const C<R> *)nullptr : (const C<R> *)w.qp.as<C<R>>(), w.r.as<C<R>>(),
-                       w.p.as<C<R>>(), N, part, (int)SLOT_RR0, sc);
+                       b_less_gram ? (const C<R> *)nullptr : (const C<R> *)w.qp, w.r, w.p, N, part, (int)SLOT_RR0,
+                       sc);
     RIOP_HIP(hipGetLastError());
     // Where the FFT's column passes can, they apply the direction update
     // (before transforming p) and form q + 2 p with its p.q partials (after);
@@ -434,23 +447,22 @@ static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, double tol,
         cg.slot_pq = SLOT_PQ;
         if (k > 0) {  // p = r + beta p, beta = rr[cur] / rr[previous]
             if (fold) {
-                cg.r = w.r.as<C<R>>();
+                cg.r = w.r;
                 cg.slot_old = nxt;
                 cg.slot_new = cur;
             } else {
-                VEC_LAUNCH(p, cg_direction<R>, RB(), RT(), 0, s, w.r.as<C<R>>(), w.p.as<C<R>>(), N,
-                           (const double *)part, nxt, cur);
+                VEC_LAUNCH(p, cg_direction<R>, RB(), RT(), 0, s, (const C<R> *)w.r, w.p, N, (const double *)part,
+                           nxt, cur);
             }
         }
-        if (fold) cg.p = w.p.as<C<R>>();
-        const bool d_done = launch_phi_fft_forward<R>(p, w.p.ptr, s, fold ? &cg : nullptr);
+        if (fold) cg.p = w.p;
+        const bool d_done = launch_phi_fft_forward<R>(p, w.p, s, fold ? &cg : nullptr);
         launch_gram<R>(p, p->grid.ptr, p->grid2.ptr, s);
-        const bool q_done = launch_phi_fft_adjoint<R>(p, w.qp.ptr, s, p->grid2.ptr, fold ? &cg : nullptr);
+        const bool q_done = launch_phi_fft_adjoint<R>(p, w.qp, s, p->grid2.ptr, fold ? &cg : nullptr);
         RIOP_REQUIRE(d_done == (fold && k > 0) && q_done == fold, RIOP_EDEVICE, "CG step folding mismatch");
-        if (!fold)
-            VEC_LAUNCH(p, cg_pq<R>, RB(), RT(), 0, s, w.p.as<C<R>>(), w.qp.as<C<R>>(), N, part, (int)SLOT_PQ);
-        VEC_LAUNCH(p, cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r.as<C<R>>(), w.p.as<C<R>>(),
-                           w.qp.as<C<R>>(), N, part, cur, (int)SLOT_PQ, nxt, sc, tol2, k == 0 ? 1 : 0);
+        if (!fold) VEC_LAUNCH(p, cg_pq<R>, RB(), RT(), 0, s, (const C<R> *)w.p, w.qp, N, part, (int)SLOT_PQ);
+        VEC_LAUNCH(p, cg_update<R>, RB(), RT(), 0, s, static_cast<C<R> *>(x), w.r, (const C<R> *)w.p,
+                           (const C<R> *)w.qp, N, part, cur, (int)SLOT_PQ, nxt, sc, tol2, k == 0 ? 1 : 0);
         RIOP_HIP(hipGetLastError());
         cur = nxt;
     }
@@ -571,7 +583,7 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         // Step 5: x = Q^{-1} sum_i x_i by CG, warm-started from the previous x
         // (rhs holds the sum less Phi^dagger Phi x).
         int rr_slot = SLOT_RR0;
-        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, w.cg_tol, &rr_slot, s, true);
+        cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, w.cg_tol, &rr_slot, s, plan_cg_work<R>(p), true);
         // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
         launch_psi_adj_prox<R>(p, xh, px, s);
         launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
@@ -690,25 +702,94 @@ template <typename R> static void apply_q_run(riop_plan *p, const void *x, void 
     RIOP_HIP(hipGetLastError());
 }
 
-template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x, int n_iter, double tol,
-                                           double *rr_out, int32_t *iters_out, hipStream_t s) {
+// CG with its workspace in `w`; reads back the final <r, r> and the
+// iteration count when asked (synchronises then).
+template <typename R>
+static void cg_with(riop_plan *p, const void *b, void *x, int n_iter, double tol, double *rr_out, int32_t *iters_out,
+                    hipStream_t s, const CgWork<R> &w) {
     const long N = (long)p->n * p->n;
-    ensure_work(p);
     check_finite_input(p, b, 2 * N, s);
     check_finite_input(p, x, 2 * N, s);
     int slot = SLOT_RR0;
-    cg_run<R>(p, b, x, n_iter, tol, &slot, s);
+    cg_run<R>(p, b, x, n_iter, tol, &slot, s, w);
     if (rr_out || iters_out) {
-        VEC_LAUNCH(p, slot_to_scalar, dim3(1), RT(), 0, s, (const double *)p->sd.partials.as<double>(), slot,
-                           p->sd.scalars.as<double>(), (int)SC_RRFINAL);
+        VEC_LAUNCH(p, slot_to_scalar, dim3(1), RT(), 0, s, (const double *)w.partials, slot, w.scalars,
+                   (int)SC_RRFINAL);
         RIOP_HIP(hipGetLastError());
         double sc[kScalars];
-        RIOP_HIP(hipMemcpyAsync(sc, p->sd.scalars.as<double>(), sizeof sc, hipMemcpyDeviceToHost, s));
+        RIOP_HIP(hipMemcpyAsync(sc, w.scalars, sizeof sc, hipMemcpyDeviceToHost, s));
         report_nonfinite(p, s);
         if (rr_out) *rr_out = sc[SC_RRFINAL];
         if (iters_out) *iters_out = n_iter > 0 ? (int32_t)sc[SC_CGIT] : 0;
     }
     mark_done(p, s);
+}
+
+template <typename R> static void cg_entry(riop_plan *p, const void *b, void *x, int n_iter, double tol,
+                                           double *rr_out, int32_t *iters_out, hipStream_t s) {
+    ensure_work(p);
+    cg_with<R>(p, b, x, n_iter, tol, rr_out, iters_out, s, plan_cg_work<R>(p));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free CG: the workspace lives in a static device array, one copy
+// per device the library runs on (held until the process ends).  Its device
+// address is taken once per device with hipGetSymbolAddress; host code never
+// uses the array's name as an address.
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device (set up on first use).
+static void *scratch_on_current_device() {
+    int dev = -1;
+    RIOP_HIP(hipGetDevice(&dev));
+    RIOP_REQUIRE(dev >= 0 && dev < kMaxDevices, RIOP_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        RIOP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        RIOP_REQUIRE(ptr, RIOP_EDEVICE, "scratch symbol has no device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of scratch a plan's CG needs: partial-sum and scalar slots, then
+// r, p, Q p.
+static size_t cg_scratch_bytes(const riop_plan *p) {
+    const size_t vec = align256(cbytes(p) * (size_t)p->n * p->n);
+    return align256(sizeof(double) * kSlots * kRedBlocks) + align256(sizeof(double) * kScalars) + 3 * vec;
+}
+
+template <typename R>
+static void cg_noalloc_entry(riop_plan *p, const void *b, void *x, int n_iter, double tol, double *rr_out,
+                             int32_t *iters_out, hipStream_t s) {
+    const size_t need = cg_scratch_bytes(p);
+    if (need > kScratchBytes)
+        throw Error{RIOP_ENOTSUP, "riop_cg_noalloc: the plan's CG workspace needs " + std::to_string(need) +
+                                      " bytes, more than the " + std::to_string(kScratchBytes) +
+                                      "-byte static scratch (use riop_cg)"};
+    unsigned char *base = static_cast<unsigned char *>(scratch_on_current_device());
+    const size_t vec = align256(cbytes(p) * (size_t)p->n * p->n);
+    CgWork<R> w;
+    w.partials = reinterpret_cast<double *>(base);
+    base += align256(sizeof(double) * kSlots * kRedBlocks);
+    w.scalars = reinterpret_cast<double *>(base);
+    base += align256(sizeof(double) * kScalars);
+    w.r = reinterpret_cast<C<R> *>(base);
+    w.p = reinterpret_cast<C<R> *>(base + vec);
+    w.qp = reinterpret_cast<C<R> *>(base + 2 * vec);
+    // Every slot CG reads is written earlier in the same call (cg_init and the
+    // first update set the residual norms, the iteration count and the
+    // reference norm), so nothing from an earlier call is read.
+    cg_with<R>(p, b, x, n_iter, tol, rr_out, iters_out, s, w);
 }
 
 template <typename R> static void gamma_entry(riop_plan *p, const void *y, double beta, double *g, hipStream_t s) {
@@ -770,6 +851,20 @@ riop_status riop_cg(riop_plan *p, const void *b, void *x, int32_t n_iter, double
             cg_entry<double>(p, b, x, n_iter, tol, rr_out, iters_out, static_cast<hipStream_t>(stream));
         else
             cg_entry<float>(p, b, x, n_iter, tol, rr_out, iters_out, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_cg_noalloc(riop_plan *p, const void *b, void *x, int32_t n_iter, double tol, double *rr_out,
+                            int32_t *iters_out, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(b && x && b != x, RIOP_EINVAL, "b and x must be distinct non-NULL pointers");
+        RIOP_REQUIRE(n_iter >= 0, RIOP_EINVAL, "n_iter must be >= 0");
+        RIOP_REQUIRE(tol >= 0 && std::isfinite(tol), RIOP_EINVAL, "tol must be finite and >= 0");
+        if (p->prec == RIOP_F64)
+            cg_noalloc_entry<double>(p, b, x, n_iter, tol, rr_out, iters_out, static_cast<hipStream_t>(stream));
+        else
+            cg_noalloc_entry<float>(p, b, x, n_iter, tol, rr_out, iters_out, static_cast<hipStream_t>(stream));
     });
 }
 

@@ -286,6 +286,42 @@ riop_status riop_sdmm(riop_plan *plan, const void *y, double eps,
                       const riop_sdmm_params *params, void *x_inout,
                       riop_sdmm_stats *stats, void *stream);
 
+/* Reweighted l1 (Sec. 3.3: SARA replaces the l0 prior by a sequence of
+ * weighted l1 problems of eq. delta whose weights are essentially the
+ * inverse of the previous solution's coefficients; RWBP and RWBPDb8 of Sec. 6
+ * with a one-basis dictionary).
+ *   pass 0       Algorithm 1 with W = I from x^(0) = x_inout
+ *   pass k >= 1  Algorithm 1 restarted (duals zero) from the previous solution
+ *                with w_j = delta_k / (delta_k + |alpha_j|), alpha = Psi^dagger
+ *                x_hat^(k-1), and the penalty gamma of pass 0
+ *   delta_1      delta0 if > 0, else the root mean square of |alpha| after
+ *                pass 0 (1 if that is 0); delta_{k+1} = max(rho delta_k, delta_min)
+ *   stop         after `outer` reweighted passes, or once
+ *                ||x_k - x_{k-1}|| <= tol ||x_k|| (tol > 0)
+ * The regularised inverse and the delta schedule are this library's reading:
+ * the paper defers them to its SARA reference. */
+typedef struct {
+    int32_t outer;     /* reweighted passes after the unweighted one, >= 0 */
+    double delta0;     /* delta of the first reweighting; <= 0: RMS of |alpha| */
+    double rho;        /* geometric decrease of delta, 0 < rho <= 1 */
+    double delta_min;  /* floor of delta, >= 0 */
+    double tol;        /* relative change of x that ends the passes; 0: never */
+} riop_reweight_params;
+
+/* Run the reweighted passes (synchronises).
+ *   params       T, n_cg, gamma/beta, cg_tol, xi, tau, early_stop of every pass;
+ *                weights, resume, state and history pointers must be zero
+ *   x_inout      device n*n complex, required: x^(0) in, final solution out
+ *   weights_out  nullable device q*n*n reals: the weights of the last pass
+ *                (all ones if only pass 0 ran)
+ *   stats        host, nullable: the last pass's statistics
+ *   passes       host, nullable: SDMM runs made (1 + reweighted passes)
+ * Allocates the weights and the previous solution (q n^2 reals, n^2 complex)
+ * in the plan on first use. */
+riop_status riop_sdmm_reweighted(riop_plan *plan, const void *y, double eps, const riop_sdmm_params *params,
+                                 const riop_reweight_params *rw, void *x_inout, void *weights_out,
+                                 riop_sdmm_stats *stats, int32_t *passes, void *stream);
+
 /* The same run in three phases, for callers that capture the iterations in a
  * HIP graph or interleave several plans.
  *   riop_sdmm_init    Algorithm 1 steps 1-3 (or a resumed state), the penalty

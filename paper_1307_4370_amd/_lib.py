@@ -26,7 +26,7 @@ EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan
            "riop_plan_sync", "riop_device_bytes", "riop_noise_bound",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_cg_noalloc", "riop_gamma",
-           "riop_sdmm", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
+           "riop_sdmm", "riop_sdmm_reweighted", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
            "riop_batch_destroy", "riop_autotune_tile", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
            "riop_timing_name", "riop_last_error", "riop_version")
 
@@ -64,6 +64,11 @@ class SdmmParams(ctypes.Structure):
 HIST = 5  # doubles per iteration in the SDMM history: f1, zeta, nu, CG <r, r>, CG iterations
 
 
+class ReweightParams(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("delta0", ctypes.c_double), ("rho", ctypes.c_double),
+                ("delta_min", ctypes.c_double), ("tol", ctypes.c_double)]
+
+
 class SdmmStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("gamma", ctypes.c_double), ("f1", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("nu", ctypes.c_double), ("status_iter", ctypes.c_int32),
@@ -97,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.riop_sdmm.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp,
                                 ctypes.POINTER(SdmmStats), vp]
         L.riop_sdmm_init.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp, vp]
+        L.riop_sdmm_reweighted.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), ctypes.POINTER(ReweightParams),
+                                           vp, vp, ctypes.POINTER(SdmmStats), ctypes.POINTER(i32), vp]
         L.riop_sdmm_step.argtypes = [vp, i32, vp]
         L.riop_sdmm_finish.argtypes = [vp, ctypes.POINTER(SdmmParams), vp, ctypes.POINTER(SdmmStats), vp]
         L.riop_batch_create.argtypes = [ctypes.POINTER(Desc), i32, ctypes.POINTER(vp), i32, vp,
@@ -310,6 +317,29 @@ class Plan:
         state["f1_prev"] = st.f1 if st.iters else state["f1_prev"]
         stats = {k: getattr(st, k) for k, _ in SdmmStats._fields_}
         return x, stats, history, state
+
+
+    def sdmm_reweighted(self, y, eps: float, T: int, n_cg: int = 16, outer: int = 3, delta0: float = 0.0,
+                        rho: float = 0.1, delta_min: float = 0.0, tol: float = 0.0, gamma: float = 0.0,
+                        beta: float = 1e-3, x0=None, cg_tol: float = 0.0, early_stop: bool = False,
+                        xi: float = 1e-3, tau: float = 0.1, stream=None):
+        """Reweighted l1 (SARA): pass 0 with W = I, then up to `outer` passes
+        with w = delta / (delta + |Psi^dagger x|).  Returns (x, stats of the
+        last pass, passes run, weights of the last pass)."""
+        y = self._c(y, (self.M,), "y")
+        n = self.n
+        x = (torch.zeros((n, n), dtype=self.cdtype, device=self.device) if x0 is None
+             else self._c(x0, (n, n), "x0").clone())
+        w = torch.empty((self.q, n, n), dtype=self.rdtype, device=self.device)
+        prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=xi, tau=tau, early_stop=int(early_stop),
+                         cg_tol=float(cg_tol))
+        rw = ReweightParams(outer=outer, delta0=delta0, rho=rho, delta_min=delta_min, tol=tol)
+        st = SdmmStats()
+        passes = ctypes.c_int32()
+        _check(lib().riop_sdmm_reweighted(self._h, y.data_ptr(), float(eps), ctypes.byref(prm), ctypes.byref(rw),
+                                          x.data_ptr(), w.data_ptr(), ctypes.byref(st), ctypes.byref(passes),
+                                          _stream(stream)))
+        return x, {k: getattr(st, k) for k, _ in SdmmStats._fields_}, passes.value, w
 
 
 class _BorrowedPlan(Plan):

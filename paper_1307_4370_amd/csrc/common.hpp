@@ -148,6 +148,8 @@ struct SdmmWork {
     DevBuf f1part;          // per analysis block partials of f1 (psi_adj_blocks doubles)
     int f1_count = 0;
     DevBuf scalars;         // doubles: scalar slots
+    DevBuf rw_w;            // reweighted l1: the current weights (q*N reals)
+    DevBuf xprev;           // reweighted l1: the previous pass's solution (N complex)
     DevBuf history;         // doubles, kHistStride per iteration
     int hist_cap = 0;       // iterations the history buffer holds (grows only)
     int n_cg = 0;

@@ -306,6 +306,11 @@ __global__ void prox3_rhs(const C<R> *xh, C<R> *z3, const C<R> *x1, const C<R> *
     }
 }
 
+// out = v (reals)
+template <typename R> __global__ void fill_real(R *out, long n, R v) {
+    GRID_LOOP(i, n) out[i] = v;
+}
+
 // out = a + sb b (sb = +1 or -1)
 template <typename R> __global__ void lin2(const C<R> *a, const C<R> *b, R sb, C<R> *out, long N) {
     GRID_LOOP(i, N) {
@@ -346,6 +351,37 @@ __global__ void record_stats(const double *partials, double *scalars, double *hi
         scalars[SC_F1PREV] = f1;
         scalars[SC_RRFINAL] = rr;
         scalars[SC_ITER] = (double)(t + 1);
+    }
+}
+
+// Reweighted l1 (Sec. 3.3): w_j = delta / (delta + |alpha_j|).
+template <typename R> __global__ void reweight_weights(const C<R> *alpha, R *w, long D, double delta) {
+    GRID_LOOP(i, D) w[i] = (R)(delta / (delta + sqrt(abs2<R>(alpha[i]))));
+}
+
+// slot <- sum |a|^2
+template <typename R> __global__ void sum_abs2(const C<R> *a, long n, double *partials, int slot) {
+    double acc = 0;
+    GRID_LOOP(i, n) acc += abs2<R>(a[i]);
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = s;
+}
+
+// slot_d <- sum |x - xp|^2, slot_x <- sum |x|^2
+template <typename R>
+__global__ void diff_norms(const C<R> *x, const C<R> *xp, long n, double *partials, int slot_d, int slot_x) {
+    double d = 0, t = 0;
+    GRID_LOOP(i, n) {
+        const C<R> a = x[i], b = xp[i];
+        const double dr = (double)a.x - b.x, di = (double)a.y - b.y;
+        d += dr * dr + di * di;
+        t += abs2<R>(a);
+    }
+    const double sd = block_sum(d);
+    const double st = block_sum(t);
+    if (threadIdx.x == 0) {
+        partials[slot_d * kRedBlocks + blockIdx.x] = sd;
+        partials[slot_x * kRedBlocks + blockIdx.x] = st;
     }
 }
 
@@ -692,6 +728,83 @@ static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_pa
     sdmm_finish<R>(p, prm, x_inout, stats, prm->history, s, stop_iter);
 }
 
+// Sum of one partial-sum slot, read back to the host (synchronises).
+static double slot_to_host(riop_plan *p, int slot, hipStream_t s) {
+    VEC_LAUNCH(p, slot_to_scalar, dim3(1), RT(), 0, s, (const double *)p->sd.partials.as<double>(), slot,
+               p->sd.scalars.as<double>(), (int)SC_RRFINAL);
+    RIOP_HIP(hipGetLastError());
+    double v = 0;
+    RIOP_HIP(hipMemcpyAsync(&v, p->sd.scalars.as<double>() + SC_RRFINAL, sizeof v, hipMemcpyDeviceToHost, s));
+    RIOP_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+// Reweighted l1 (Sec. 3.3, the sequence of weighted problems of eq. delta):
+// pass 0 with W = I, then up to rw->outer passes with
+// w = delta / (delta + |Psi^dagger x_prev|), each a fresh run of Algorithm 1
+// from the previous solution with the first pass's penalty.
+template <typename R>
+static void reweighted_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *inner,
+                           const riop_reweight_params *rw, void *x, void *weights_out, riop_sdmm_stats *stats,
+                           int32_t *passes_out, hipStream_t s) {
+    ensure_work(p);
+    SdmmWork &w = p->sd;
+    const long N = (long)p->n * p->n, D = (long)p->q * N;
+    const size_t cb = cbytes(p);
+    w.rw_w.reserve(rbytes(p) * (size_t)D);
+    w.xprev.reserve(cb * (size_t)N);
+    riop_sdmm_params prm = *inner;
+    prm.weights = nullptr;
+    prm.resume = 0;
+    prm.z1 = prm.z2 = prm.z3 = prm.rhs = nullptr;
+    prm.history = nullptr;
+    riop_sdmm_stats st{};
+    double *part = w.partials.as<double>();
+    sdmm_run<R>(p, y, eps, &prm, x, &st, s);
+    prm.gamma = st.gamma;
+    int passes = 1;
+    double delta = 0.0;
+    for (int k = 0; k < rw->outer; ++k) {
+        // Weights from the current solution's coefficients.
+        launch_psi_adj<R>(p, x, w.w1.ptr, s);
+        if (k == 0) {
+            if (rw->delta0 > 0) {
+                delta = rw->delta0;
+            } else {
+                VEC_LAUNCH(p, sum_abs2<R>, RB(), RT(), 0, s, (const C<R> *)w.w1.as<C<R>>(), D, part, (int)SLOT_MAX);
+                const double ms = slot_to_host(p, SLOT_MAX, s) / (double)D;
+                delta = ms > 0 ? std::sqrt(ms) : 1.0;
+            }
+        } else {
+            delta = std::max(rw->rho * delta, rw->delta_min);
+        }
+        VEC_LAUNCH(p, reweight_weights<R>, RB(), RT(), 0, s, (const C<R> *)w.w1.as<C<R>>(), w.rw_w.as<R>(), D,
+                   delta);
+        RIOP_HIP(hipMemcpyAsync(w.xprev.ptr, x, cb * N, hipMemcpyDeviceToDevice, s));
+        prm.weights = w.rw_w.ptr;
+        sdmm_run<R>(p, y, eps, &prm, x, &st, s);
+        ++passes;
+        if (rw->tol > 0) {
+            VEC_LAUNCH(p, diff_norms<R>, RB(), RT(), 0, s, (const C<R> *)x, (const C<R> *)w.xprev.as<C<R>>(), N,
+                       part, (int)SLOT_E, (int)SLOT_NU);
+            const double d2 = slot_to_host(p, SLOT_E, s), x2 = slot_to_host(p, SLOT_NU, s);
+            const double change = x2 > 0 ? std::sqrt(d2 / x2) : 0.0;
+            if (change <= rw->tol) break;
+        }
+    }
+    if (weights_out) {
+        if (passes == 1) {  // only the unweighted pass ran: W = I
+            VEC_LAUNCH(p, fill_real<R>, RB(), RT(), 0, s, static_cast<R *>(weights_out), D, R(1));
+        } else {
+            RIOP_HIP(hipMemcpyAsync(weights_out, w.rw_w.ptr, rbytes(p) * (size_t)D, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    RIOP_HIP(hipStreamSynchronize(s));
+    mark_done(p, s);
+    if (stats) *stats = st;
+    if (passes_out) *passes_out = passes;
+}
+
 template <typename R> static void apply_q_run(riop_plan *p, const void *x, void *out, hipStream_t s) {
     const long N = (long)p->n * p->n;
     ensure_work(p);
@@ -893,6 +1006,32 @@ riop_status riop_sdmm(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             sdmm_run<double>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
         else
             sdmm_run<float>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm_reweighted(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm,
+                                 const riop_reweight_params *rw, void *x_inout, void *weights_out,
+                                 riop_sdmm_stats *stats, int32_t *passes, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(prm && rw && x_inout, RIOP_EINVAL, "params, reweighting params and x_inout are required");
+        RIOP_REQUIRE(y || p->M == 0, RIOP_EINVAL, "y is NULL");
+        RIOP_REQUIRE(eps > 0 && std::isfinite(eps), RIOP_EINVAL, "eps must be positive and finite");
+        RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0, RIOP_EINVAL, "T and n_cg must be >= 0");
+        RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        RIOP_REQUIRE(prm->cg_tol >= 0 && std::isfinite(prm->cg_tol), RIOP_EINVAL, "cg_tol must be finite and >= 0");
+        RIOP_REQUIRE(!prm->weights && !prm->resume && !prm->z1 && !prm->z2 && !prm->z3 && !prm->rhs && !prm->history,
+                     RIOP_EINVAL, "the reweighted run owns the weights and state: weights, resume, state and history "
+                                  "pointers must be zero");
+        RIOP_REQUIRE(rw->outer >= 0 && rw->rho > 0 && rw->rho <= 1 && rw->delta_min >= 0 && rw->tol >= 0 &&
+                         std::isfinite(rw->delta0) && std::isfinite(rw->delta_min) && std::isfinite(rw->tol),
+                     RIOP_EINVAL, "reweighting: outer >= 0, 0 < rho <= 1, delta_min >= 0, tol >= 0, finite delta0");
+        if (p->prec == RIOP_F64)
+            reweighted_run<double>(p, y, eps, prm, rw, x_inout, weights_out, stats, passes,
+                                   static_cast<hipStream_t>(stream));
+        else
+            reweighted_run<float>(p, y, eps, prm, rw, x_inout, weights_out, stats, passes,
+                                  static_cast<hipStream_t>(stream));
     });
 }
 

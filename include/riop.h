@@ -286,6 +286,31 @@ riop_status riop_sdmm(riop_plan *plan, const void *y, double eps,
                       const riop_sdmm_params *params, void *x_inout,
                       riop_sdmm_stats *stats, void *stream);
 
+/* Block SDMM (Sec. 4.5, eqs. blocks, dbp1, dbp2): the visibilities are split
+ * into R blocks, each with its own data constraint ||y_i - Phi_i x|| <= eps_i,
+ * and Algorithm 1 runs with S = R + 2 terms: L1 = Psi^dagger (l1), L2 = I
+ * (positivity), L_{i+2} = Phi_i (the l2 ball of block i).  Q is unchanged,
+ * since sum_i Phi_i^dagger Phi_i = Phi^dagger Phi; the blocks' steps 7-9 run
+ * together and sum_i Phi_i^dagger (r_i - z_i) is one Phi^dagger of the
+ * concatenated values.  This is the one-GPU form of the paper's distributed
+ * split (each block's data and duals would live on its own node).
+ *   y         device M complex (caller order)
+ *   nblocks   R, 1 <= R <= 1024
+ *   block_of  device int32[M], caller order: the block of each visibility;
+ *             a value outside [0, R) -> RIOP_EINVAL (synchronises to check)
+ *   eps       host double[R], each > 0
+ *   params    as riop_sdmm (T, n_cg, gamma/beta, cg_tol, weights, early_stop,
+ *             history, state outputs z1/z2/z3/rhs); resume must be 0
+ *   x_inout   nullable device n*n complex: x^(0) in (NULL: 0), x^(T) out
+ *   stats     host, nullable; stats->nu and the history's nu are the largest
+ *             ||y_i - Phi_i x|| / eps_i over the blocks
+ *   nu_out    host, nullable, R doubles: every block's ratio at the last
+ *             iteration
+ * The halting rule (early_stop) uses the largest ratio.  Synchronises. */
+riop_status riop_sdmm_blocks(riop_plan *plan, const void *y, int32_t nblocks, const int32_t *block_of,
+                             const double *eps, const riop_sdmm_params *params, void *x_inout,
+                             riop_sdmm_stats *stats, double *nu_out, void *stream);
+
 /* Reweighted l1 (Sec. 3.3: SARA replaces the l0 prior by a sequence of
  * weighted l1 problems of eq. delta whose weights are essentially the
  * inverse of the previous solution's coefficients; RWBP and RWBPDb8 of Sec. 6

@@ -26,7 +26,7 @@ EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan
            "riop_plan_sync", "riop_device_bytes", "riop_noise_bound",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_cg_noalloc", "riop_gamma",
-           "riop_sdmm", "riop_sdmm_reweighted", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
+           "riop_sdmm", "riop_sdmm_reweighted", "riop_sdmm_blocks", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
            "riop_batch_destroy", "riop_autotune_tile", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
            "riop_timing_name", "riop_last_error", "riop_version")
 
@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.riop_sdmm.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp,
                                 ctypes.POINTER(SdmmStats), vp]
         L.riop_sdmm_init.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp, vp]
+        L.riop_sdmm_blocks.argtypes = [vp, vp, i32, vp, ctypes.POINTER(dbl), ctypes.POINTER(SdmmParams), vp,
+                                       ctypes.POINTER(SdmmStats), ctypes.POINTER(dbl), vp]
         L.riop_sdmm_reweighted.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), ctypes.POINTER(ReweightParams),
                                            vp, vp, ctypes.POINTER(SdmmStats), ctypes.POINTER(i32), vp]
         L.riop_sdmm_step.argtypes = [vp, i32, vp]
@@ -318,6 +320,36 @@ class Plan:
         stats = {k: getattr(st, k) for k, _ in SdmmStats._fields_}
         return x, stats, history, state
 
+
+    def sdmm_blocks(self, y, eps, block_of, T: int, n_cg: int = 16, gamma: float = 0.0, beta: float = 1e-3,
+                    x0=None, weights=None, cg_tol: float = 0.0, early_stop: bool = False, xi: float = 1e-3,
+                    tau: float = 0.1, stream=None):
+        """Block SDMM: one l2 ball per data block.  block_of: int32 tensor (M,)
+        of block indices in caller order; eps: one bound per block.  Returns
+        (x, stats, history, per-block nu at the last iteration)."""
+        y = self._c(y, (self.M,), "y")
+        R = len(eps)
+        if block_of.dtype != torch.int32 or tuple(block_of.shape) != (self.M,) or block_of.device != self.device:
+            raise ValueError(f"block_of must be an int32 tensor of shape ({self.M},) on {self.device}")
+        block_of = block_of.contiguous()
+        n = self.n
+        x = (torch.zeros((n, n), dtype=self.cdtype, device=self.device) if x0 is None
+             else self._c(x0, (n, n), "x0").clone())
+        w = None
+        if weights is not None:
+            if weights.dtype != self.rdtype or tuple(weights.shape) != (self.q, n, n):
+                raise ValueError("weights must be a real tensor of shape (q, n, n)")
+            w = weights.contiguous()
+        hist = (ctypes.c_double * (HIST * max(1, T)))()
+        prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=xi, tau=tau, early_stop=int(early_stop),
+                         weights=_ptr(w), history=hist, cg_tol=float(cg_tol))
+        st = SdmmStats()
+        ep = (ctypes.c_double * R)(*[float(e) for e in eps])
+        nu = (ctypes.c_double * R)()
+        _check(lib().riop_sdmm_blocks(self._h, y.data_ptr(), R, block_of.data_ptr(), ep, ctypes.byref(prm),
+                                      x.data_ptr(), ctypes.byref(st), nu, _stream(stream)))
+        history = [tuple(hist[HIST * t:HIST * t + HIST]) for t in range(min(st.iters, T))]
+        return x, {k: getattr(st, k) for k, _ in SdmmStats._fields_}, history, list(nu)
 
     def sdmm_reweighted(self, y, eps: float, T: int, n_cg: int = 16, outer: int = 3, delta0: float = 0.0,
                         rho: float = 0.1, delta_min: float = 0.0, tol: float = 0.0, gamma: float = 0.0,

@@ -148,6 +148,11 @@ struct SdmmWork {
     DevBuf f1part;          // per analysis block partials of f1 (psi_adj_blocks doubles)
     int f1_count = 0;
     DevBuf scalars;         // doubles: scalar slots
+    // Block SDMM (R data blocks): each visibility's block in plan order
+    // (int32 M), per-block eps, ball scale and nu (R doubles each), and the
+    // reduction blocks' partial norms (kRedBlocks * 2R doubles).
+    int nblocks = 0;
+    DevBuf blk, beps, bscale, bnu, bpart, bflag;
     DevBuf rw_w;            // reweighted l1: the current weights (q*N reals)
     DevBuf xprev;           // reweighted l1: the previous pass's solution (N complex)
     DevBuf history;         // doubles, kHistStride per iteration

@@ -354,6 +354,100 @@ __global__ void record_stats(const double *partials, double *scalars, double *hi
     }
 }
 
+// ---------------------------------------------------------------------------
+// Block SDMM (Sec. 4.5): one l2 ball per data block, blk[i] the block of
+// plan-order visibility i.
+
+constexpr int kMaxBlocks = 1024;
+
+// Per reduction block, for every data block b: sum |s + z2 - y|^2 and
+// sum |y - s|^2 over its visibilities, accumulated in LDS (a wavefront whose
+// live visibilities share one block adds its wave sum with one atomic).
+template <typename R>
+__global__ void prox2_norms_blocks(const C<R> *s, const C<R> *z2, const C<R> *y, const int *blk, long M, int nb,
+                                   double *bpart) {
+    extern __shared__ double sh[];  // 2 nb
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) sh[i] = 0.0;
+    __syncthreads();
+    for (long i0 = (long)blockIdx.x * blockDim.x; i0 < M; i0 += (long)gridDim.x * blockDim.x) {
+        const long i = i0 + threadIdx.x;
+        const bool live = i < M;
+        int b = -1;
+        double e = 0.0, nu = 0.0;
+        if (live) {
+            b = blk[i];
+            const C<R> si = s[i], zi = z2[i], yi = y[i];
+            const double dr = (double)si.x + zi.x - yi.x, di = (double)si.y + zi.y - yi.y;
+            const double fr = (double)yi.x - si.x, fi = (double)yi.y - si.y;
+            e = dr * dr + di * di;
+            nu = fr * fr + fi * fi;
+        }
+        const int bref = __shfl(b, 0);
+        if (__all(!live || b == bref) && bref >= 0) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                e += __shfl_xor(e, o);
+                nu += __shfl_xor(nu, o);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                atomicAdd(&sh[2 * bref], e);
+                atomicAdd(&sh[2 * bref + 1], nu);
+            }
+        } else if (live) {
+            atomicAdd(&sh[2 * b], e);
+            atomicAdd(&sh[2 * b + 1], nu);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) bpart[(long)blockIdx.x * 2 * nb + i] = sh[i];
+}
+
+// Per data block: scale = min(1, eps_b / ||v_b - y_b||), nu_b = ||y_b - s_b|| / eps_b
+// (partials summed in a fixed order); the largest nu_b, squared, becomes the
+// only nonzero partial of SLOT_NU (the history's nu, with SC_EPS = 1).
+__global__ void block_scales(const double *bpart, int nb, const double *beps, double *bscale, double *bnu,
+                             double *partials) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        double e2 = 0.0, n2 = 0.0;
+        for (int w = 0; w < kRedBlocks; ++w) {
+            e2 += bpart[(long)w * 2 * nb + 2 * b];
+            n2 += bpart[(long)w * 2 * nb + 2 * b + 1];
+        }
+        const double e = sqrt(e2), eps = beps[b];
+        bscale[b] = e > eps ? eps / e : 1.0;
+        bnu[b] = sqrt(n2) / eps;
+        m = fmax(m, bnu[b]);
+    }
+    m = block_max(m);
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) partials[SLOT_NU * kRedBlocks + i] = i ? 0.0 : m * m;
+}
+
+// The balls' projections and duals, and the values for Phi^dagger:
+// v = s + z2, r = y + (v - y) scale_b, z2 <- v - r, d = r - z2 - s.
+template <typename R>
+__global__ void prox2_apply_blocks(const C<R> *s, C<R> *z2, const C<R> *y, const int *blk, const double *bscale,
+                                   C<R> *d, long M) {
+    GRID_LOOP(i, M) {
+        const C<R> si = s[i], zi = z2[i], yi = y[i];
+        const double sc = bscale[blk[i]];
+        const double vr = (double)si.x + zi.x, vi = (double)si.y + zi.y;
+        const double rr = yi.x + (vr - yi.x) * sc, ri = yi.y + (vi - yi.y) * sc;
+        const double znr = vr - rr, zni = vi - ri;
+        z2[i] = mk<R>((R)znr, (R)zni);
+        d[i] = mk<R>((R)(rr - znr - si.x), (R)(ri - zni - si.y));
+    }
+}
+
+// blk[i] = block_of[perm[i]]; flag <- 1 if a block index is outside [0, nb).
+__global__ void gather_blocks(const int *block_of, const int *perm, long M, int nb, int *blk, int *flag) {
+    GRID_LOOP(i, M) {
+        const int b = block_of[perm[i]];
+        if (b < 0 || b >= nb) atomicOr(flag, 1);
+        blk[i] = b < 0 ? 0 : (b >= nb ? nb - 1 : b);
+    }
+}
+
 // Reweighted l1 (Sec. 3.3): w_j = delta / (delta + |alpha_j|).
 template <typename R> __global__ void reweight_weights(const C<R> *alpha, R *w, long D, double delta) {
     GRID_LOOP(i, D) w[i] = (R)(delta / (delta + sqrt(abs2<R>(alpha[i]))));
@@ -537,7 +631,8 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
         ++w.epoch;
     }
     w.hist_cap = (int)std::min<size_t>(w.history.bytes / (sizeof(double) * kHistStride), 1u << 30);
-    if (w.n_cg != prm->n_cg || w.weights != prm->weights || w.cg_tol != prm->cg_tol) ++w.epoch;
+    if (w.n_cg != prm->n_cg || w.weights != prm->weights || w.cg_tol != prm->cg_tol || w.nblocks != 0) ++w.epoch;
+    w.nblocks = 0;  // a blocked run sets it after this initialisation
     w.n_cg = prm->n_cg;
     w.weights = prm->weights;
     w.cg_tol = prm->cg_tol;
@@ -626,10 +721,26 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2),
         // taken as Phi^dagger (r2 - z2 - Phi xhat) for the next warm start.
         phi_into_s2<R>(p, xh, s);
-        VEC_LAUNCH(p, prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(), w.ysort.as<C<R>>(),
-                   M, part);
-        VEC_LAUNCH(p, prox2_scale, dim3(1), RT(), 0, s, (const double *)part, sc);
-        launch_grid_prox2<R>(p, w.s2.ptr, w.z2loc.ptr, w.ysort.ptr, sc + SC_P2SCALE, s);
+        if (w.nblocks == 0) {
+            VEC_LAUNCH(p, prox2_norms<R>, RB(), RT(), 0, s, w.s2.as<C<R>>(), w.z2loc.as<C<R>>(),
+                       w.ysort.as<C<R>>(), M, part);
+            VEC_LAUNCH(p, prox2_scale, dim3(1), RT(), 0, s, (const double *)part, sc);
+            launch_grid_prox2<R>(p, w.s2.ptr, w.z2loc.ptr, w.ysort.ptr, sc + SC_P2SCALE, s);
+        } else {
+            // Block SDMM (Sec. 4.5): one ball per data block; steps 7-9 of
+            // every block i + 2 at once, sum_i Phi_i^dagger (r_i - z_i) as one
+            // Phi^dagger of the concatenated values.
+            const int nb = w.nblocks;
+            VEC_LAUNCH(p, prox2_norms_blocks<R>, RB(), RT(), sizeof(double) * 2 * nb, s,
+                       (const C<R> *)w.s2.as<C<R>>(), (const C<R> *)w.z2loc.as<C<R>>(),
+                       (const C<R> *)w.ysort.as<C<R>>(), (const int *)w.blk.as<int>(), M, nb, w.bpart.as<double>());
+            VEC_LAUNCH(p, block_scales, dim3(1), RT(), 0, s, (const double *)w.bpart.as<double>(), nb,
+                       (const double *)w.beps.as<double>(), w.bscale.as<double>(), w.bnu.as<double>(), part);
+            VEC_LAUNCH(p, prox2_apply_blocks<R>, RB(), RT(), 0, s, (const C<R> *)w.s2.as<C<R>>(),
+                       w.z2loc.as<C<R>>(), (const C<R> *)w.ysort.as<C<R>>(), (const int *)w.blk.as<int>(),
+                       (const double *)w.bscale.as<double>(), p->vis.as<C<R>>(), M);
+            launch_grid<R>(p, p->vis.ptr, 0, s);
+        }
         launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
         // i = 3 and the next right-hand side.
         VEC_LAUNCH(p, prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(), w.x1.as<C<R>>(),
@@ -725,6 +836,59 @@ static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_pa
             }
         }
     }
+    sdmm_finish<R>(p, prm, x_inout, stats, prm->history, s, stop_iter);
+}
+
+// Block SDMM (Sec. 4.5, eqs. blocks, dbp1, dbp2): Algorithm 1 with S = R + 2.
+// Q and the l1 and positivity steps are those of the plain run; the data
+// term is one l2 ball per block.
+template <typename R>
+static void sdmm_blocks_run(riop_plan *p, const void *y, int nb, const int32_t *block_of, const double *eps,
+                            const riop_sdmm_params *prm, void *x_inout, riop_sdmm_stats *stats, double *nu_out,
+                            hipStream_t s) {
+    ensure_work(p);
+    SdmmWork &w = p->sd;
+    const long M = (long)p->M;
+    w.blk.reserve(sizeof(int) * (size_t)std::max<long>(1, M));
+    w.beps.reserve(sizeof(double) * kMaxBlocks);
+    w.bscale.reserve(sizeof(double) * kMaxBlocks);
+    w.bnu.reserve(sizeof(double) * kMaxBlocks);
+    w.bpart.reserve(sizeof(double) * 2 * (size_t)kMaxBlocks * kRedBlocks);
+    w.bflag.reserve(sizeof(int));
+    RIOP_HIP(hipMemsetAsync(w.bflag.ptr, 0, sizeof(int), s));
+    if (M > 0)
+        VEC_LAUNCH(p, gather_blocks, RB(), RT(), 0, s, (const int *)block_of, (const int *)p->perm.as<int>(), M, nb,
+                   w.blk.as<int>(), w.bflag.as<int>());
+    RIOP_HIP(hipMemcpyAsync(w.beps.ptr, eps, sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    int bad = 0;
+    RIOP_HIP(hipMemcpyAsync(&bad, w.bflag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    RIOP_HIP(hipStreamSynchronize(s));
+    RIOP_REQUIRE(!bad, RIOP_EINVAL, "block_of holds a block index outside [0, nblocks)");
+    // eps enters through the blocks; the history's nu is already the largest
+    // per-block ratio, so the state's eps slot holds 1.
+    sdmm_init<R>(p, y, 1.0, prm, x_inout, s);
+    w.nblocks = nb;
+    ++w.epoch;
+    report_nonfinite(p, s);
+    const int T = std::max(0, prm->T);
+    int stop_iter = 0;
+    if (!prm->early_stop) {
+        sdmm_step<R>(p, T, s);
+    } else {
+        double h[kHistStride];
+        for (int t = 0; t < T; ++t) {
+            sdmm_step<R>(p, 1, s);
+            RIOP_HIP(hipMemcpyAsync(h, w.history.as<double>() + (size_t)kHistStride * t, sizeof h,
+                                    hipMemcpyDeviceToHost, s));
+            RIOP_HIP(hipStreamSynchronize(s));
+            if (!std::isfinite(h[0]) || !std::isfinite(h[2])) break;
+            if (h[1] < prm->xi && h[2] >= 1.0 - prm->tau && h[2] <= 1.0 + prm->tau) {
+                stop_iter = t + 1;
+                break;
+            }
+        }
+    }
+    if (nu_out) RIOP_HIP(hipMemcpyAsync(nu_out, w.bnu.ptr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
     sdmm_finish<R>(p, prm, x_inout, stats, prm->history, s, stop_iter);
 }
 
@@ -1006,6 +1170,29 @@ riop_status riop_sdmm(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             sdmm_run<double>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
         else
             sdmm_run<float>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm_blocks(riop_plan *p, const void *y, int32_t nblocks, const int32_t *block_of, const double *eps,
+                             const riop_sdmm_params *prm, void *x_inout, riop_sdmm_stats *stats, double *nu_out,
+                             void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(prm && eps, RIOP_EINVAL, "params and eps are required");
+        RIOP_REQUIRE(nblocks >= 1 && nblocks <= kMaxBlocks, RIOP_EINVAL, "nblocks must be in [1, 1024]");
+        RIOP_REQUIRE((y && block_of) || p->M == 0, RIOP_EINVAL, "y and block_of are required");
+        for (int b = 0; b < nblocks; ++b)
+            RIOP_REQUIRE(eps[b] > 0 && std::isfinite(eps[b]), RIOP_EINVAL, "every eps must be positive and finite");
+        RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0, RIOP_EINVAL, "T and n_cg must be >= 0");
+        RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        RIOP_REQUIRE(prm->cg_tol >= 0 && std::isfinite(prm->cg_tol), RIOP_EINVAL, "cg_tol must be finite and >= 0");
+        RIOP_REQUIRE(!prm->resume, RIOP_ENOTSUP, "block SDMM starts from x^(0); resume is not supported");
+        if (p->prec == RIOP_F64)
+            sdmm_blocks_run<double>(p, y, nblocks, block_of, eps, prm, x_inout, stats, nu_out,
+                                    static_cast<hipStream_t>(stream));
+        else
+            sdmm_blocks_run<float>(p, y, nblocks, block_of, eps, prm, x_inout, stats, nu_out,
+                                   static_cast<hipStream_t>(stream));
     });
 }
 

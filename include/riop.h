@@ -347,6 +347,32 @@ riop_status riop_sdmm_reweighted(riop_plan *plan, const void *y, double eps, con
                                  const riop_reweight_params *rw, void *x_inout, void *weights_out,
                                  riop_sdmm_stats *stats, int32_t *passes, void *stream);
 
+/* Weighted TV problems (Sec. 3.3 eq. tvproblem; Sec. 5: weighted TV
+ * ||W grad x||_1 with its prox computed by the fast iterative method of Beck
+ * and Teboulle; Sec. 6: TV with positivity, TV and RWTV):
+ *     min ||W grad x||_1  subject to  ||y - Phi x||_2 <= eps,  x >= 0
+ * by Algorithm 1 with S = 3: L1 = I (prox of gamma ||W grad .||_1 by n_inner
+ * iterations of fast gradient projection on the dual, started at zero, step
+ * 1/(8 gamma)), L2 = Phi, L3 = I; Q = Phi^dagger Phi + 2 I as for SARA.  The
+ * gradient is the forward difference, zero across the last row and column;
+ * complex images count as real vectors of twice the length (gradient
+ * magnitude sqrt(|dx|^2 + |dy|^2)); gamma <= 0 selects beta ||Phi^dagger y||_inf.
+ *   params       as riop_sdmm; params->weights (nullable) are n*n reals, one
+ *                per pixel's gradient magnitude; z1 (state) is n*n complex
+ *   n_inner      dual iterations per prox (>= 0; 0 makes the prox the identity)
+ *   rw           NULL: one run with params->weights (TV, or weighted TV).
+ *                Non-NULL: the reweighted passes of riop_sdmm_reweighted
+ *                (RWTV) with w_ij = delta / (delta + |(grad x)_ij|), delta_1 the
+ *                RMS of the gradient magnitudes unless given; x_inout then
+ *                required, params->weights and state pointers zero
+ *   weights_out  nullable device n*n reals (reweighted runs only): the last
+ *                pass's weights
+ *   passes       host, nullable: SDMM runs made
+ * Synchronises. */
+riop_status riop_sdmm_tv(riop_plan *plan, const void *y, double eps, const riop_sdmm_params *params,
+                         int32_t n_inner, const riop_reweight_params *rw, void *x_inout, void *weights_out,
+                         riop_sdmm_stats *stats, int32_t *passes, void *stream);
+
 /* The same run in three phases, for callers that capture the iterations in a
  * HIP graph or interleave several plans.
  *   riop_sdmm_init    Algorithm 1 steps 1-3 (or a resumed state), the penalty

@@ -73,3 +73,28 @@ def sdmm_reweighted(y, eps, op, sara, T, n_cg=16, outer=3, gamma=None, beta=1e-3
         alpha = sara.psi_adj(x)
         delta = max(rho * delta, delta_min)
     return x, passes, info
+
+
+def sdmm_tv_reweighted(y, eps, op, T, n_cg=16, n_inner=20, outer=3, gamma=None, beta=1e-3, x0=None,
+                       delta0=0.0, rho=0.1, delta_min=0.0, tol=0.0):
+    """Reweighted TV (RWTV, Sec. 5 and Sec. 6): the same passes as
+    :func:`sdmm_reweighted` with the weighted TV problem of oracle/tv.py and
+    w_ij = delta / (delta + |(grad x)_ij|); delta_1 from the gradient
+    magnitudes of the first solution."""
+    from . import tv
+    x, _, hist, gamma = tv.sdmm_tv(y, eps, op, T, n_cg, n_inner, gamma=gamma, beta=beta, x0=x0)
+    info = [{"delta": None, "nu": hist[-1]["nu"] if hist else 0.0, "change": None}]
+    delta = first_delta(tv.magnitude(x), delta0)
+    passes = 1
+    for _ in range(outer):
+        w = tv.tv_weights(x, delta)
+        x_new, _, hist, _ = tv.sdmm_tv(y, eps, op, T, n_cg, n_inner, gamma=gamma, weights=w, x0=x)
+        nx = float(np.linalg.norm(x_new))
+        change = float(np.linalg.norm(x_new - x)) / nx if nx > 0 else 0.0
+        info.append({"delta": delta, "nu": hist[-1]["nu"] if hist else 0.0, "change": change, "weights": w})
+        x = x_new
+        passes += 1
+        if tol > 0 and change <= tol:
+            break
+        delta = max(rho * delta, delta_min)
+    return x, passes, info

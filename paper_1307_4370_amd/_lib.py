@@ -26,7 +26,7 @@ EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan
            "riop_plan_sync", "riop_device_bytes", "riop_noise_bound",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_cg_noalloc", "riop_gamma",
-           "riop_sdmm", "riop_sdmm_reweighted", "riop_sdmm_blocks", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
+           "riop_sdmm", "riop_sdmm_reweighted", "riop_sdmm_blocks", "riop_sdmm_tv", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
            "riop_batch_destroy", "riop_autotune_tile", "riop_sdmm_init", "riop_sdmm_step", "riop_sdmm_finish", "riop_timing_enable", "riop_timing_read", "riop_timing_kinds",
            "riop_timing_name", "riop_last_error", "riop_version")
 
@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.riop_sdmm.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp,
                                 ctypes.POINTER(SdmmStats), vp]
         L.riop_sdmm_init.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), vp, vp]
+        L.riop_sdmm_tv.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), i32, ctypes.POINTER(ReweightParams), vp,
+                                   vp, ctypes.POINTER(SdmmStats), ctypes.POINTER(i32), vp]
         L.riop_sdmm_blocks.argtypes = [vp, vp, i32, vp, ctypes.POINTER(dbl), ctypes.POINTER(SdmmParams), vp,
                                        ctypes.POINTER(SdmmStats), ctypes.POINTER(dbl), vp]
         L.riop_sdmm_reweighted.argtypes = [vp, vp, dbl, ctypes.POINTER(SdmmParams), ctypes.POINTER(ReweightParams),
@@ -320,6 +322,41 @@ class Plan:
         stats = {k: getattr(st, k) for k, _ in SdmmStats._fields_}
         return x, stats, history, state
 
+
+    def sdmm_tv(self, y, eps: float, T: int, n_cg: int = 16, n_inner: int = 20, weights=None, gamma: float = 0.0,
+                beta: float = 1e-3, x0=None, reweight: dict | None = None, cg_tol: float = 0.0,
+                early_stop: bool = False, xi: float = 1e-3, tau: float = 0.1, stream=None):
+        """Weighted TV with positivity (TV, or RWTV with ``reweight`` = dict of
+        outer, delta0, rho, delta_min, tol).  weights: (n, n) real tensor, one
+        per pixel's gradient magnitude.  Returns (x, stats, history, passes,
+        weights of the last pass or None)."""
+        y = self._c(y, (self.M,), "y")
+        n = self.n
+        x = (torch.zeros((n, n), dtype=self.cdtype, device=self.device) if x0 is None
+             else self._c(x0, (n, n), "x0").clone())
+        w = None
+        if weights is not None:
+            if weights.dtype != self.rdtype or tuple(weights.shape) != (n, n):
+                raise ValueError("TV weights must be a real tensor of shape (n, n)")
+            w = weights.contiguous()
+        rw, wout, hist = None, None, None
+        if reweight is not None:
+            rw = ReweightParams(outer=reweight.get("outer", 3), delta0=reweight.get("delta0", 0.0),
+                                rho=reweight.get("rho", 0.1), delta_min=reweight.get("delta_min", 0.0),
+                                tol=reweight.get("tol", 0.0))
+            wout = torch.empty((n, n), dtype=self.rdtype, device=self.device)
+        else:
+            hist = (ctypes.c_double * (HIST * max(1, T)))()
+        prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=xi, tau=tau, early_stop=int(early_stop),
+                         weights=_ptr(w), history=hist, cg_tol=float(cg_tol))
+        st = SdmmStats()
+        passes = ctypes.c_int32()
+        _check(lib().riop_sdmm_tv(self._h, y.data_ptr(), float(eps), ctypes.byref(prm), n_inner,
+                                  ctypes.byref(rw) if rw is not None else None, x.data_ptr(), _ptr(wout),
+                                  ctypes.byref(st), ctypes.byref(passes), _stream(stream)))
+        history = ([tuple(hist[HIST * t:HIST * t + HIST]) for t in range(min(st.iters, T))]
+                   if hist is not None else None)
+        return x, {k: getattr(st, k) for k, _ in SdmmStats._fields_}, history, passes.value, wout
 
     def sdmm_blocks(self, y, eps, block_of, T: int, n_cg: int = 16, gamma: float = 0.0, beta: float = 1e-3,
                     x0=None, weights=None, cg_tol: float = 0.0, early_stop: bool = False, xi: float = 1e-3,

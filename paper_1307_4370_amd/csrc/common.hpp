@@ -153,6 +153,12 @@ struct SdmmWork {
     // reduction blocks' partial norms (kRedBlocks * 2R doubles).
     int nblocks = 0;
     DevBuf blk, beps, bscale, bnu, bpart, bflag;
+    // Prior of the l1 step: 0 = analysis l1 over the SARA dictionary (L1 =
+    // Psi^dagger), 1 = weighted TV (L1 = I, prox by fast gradient projection
+    // on the dual with tv_inner iterations; buffers N complex each).
+    int prior = 0;
+    int tv_inner = 0;
+    DevBuf tvb, tvu, tvp, tvq, tvr, tvs;
     DevBuf rw_w;            // reweighted l1: the current weights (q*N reals)
     DevBuf xprev;           // reweighted l1: the previous pass's solution (N complex)
     DevBuf history;         // doubles, kHistStride per iteration

@@ -448,6 +448,139 @@ __global__ void gather_blocks(const int *block_of, const int *perm, long M, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Weighted TV prior (Sec. 3.3 eq. tvproblem, Sec. 5): the prox of
+// lam ||W grad .||_1 by fast gradient projection on the dual (Beck &
+// Teboulle), forward differences with zero last-row / last-column
+// differences; complex images are real vectors of twice the length.
+// gradT(p, q) below is the adjoint of the gradient (minus the divergence).
+
+enum Prior { PRIOR_SARA = 0, PRIOR_TV = 1 };
+
+template <typename R> __device__ inline C<R> grad_adj_at(const C<R> *p, const C<R> *q, int i, int j, int n) {
+    const long k = (long)i * n + j;
+    C<R> v = mk<R>(0, 0);
+    if (i >= 1) v = cadd<R>(v, p[k - n]);
+    if (i < n - 1) v = csub<R>(v, p[k]);
+    if (j >= 1) v = cadd<R>(v, q[k - 1]);
+    if (j < n - 1) v = csub<R>(v, q[k]);
+    return v;
+}
+
+// b = xhat + z1 (the point the prox is taken at); the dual starts at zero.
+template <typename R>
+__global__ void tv_begin(const C<R> *xh, const C<R> *z1, C<R> *b, C<R> *p, C<R> *q, C<R> *r, C<R> *s, long N) {
+    GRID_LOOP(i, N) {
+        b[i] = cadd<R>(xh[i], z1[i]);
+        const C<R> z = mk<R>(0, 0);
+        p[i] = z;
+        q[i] = z;
+        r[i] = z;
+        s[i] = z;
+    }
+}
+
+// u = b - lam gradT(r, s)
+template <typename R> __global__ void tv_u(const C<R> *b, const C<R> *r, const C<R> *s, C<R> *u, int n,
+                                           const double *lamp) {
+    const R lam = (R)*lamp;
+    GRID_LOOP(k, (long)n * n) {
+        const int i = (int)(k / n), j = (int)(k - (long)i * n);
+        const C<R> g = grad_adj_at<R>(r, s, i, j, n);
+        u[k] = mk<R>(b[k].x - lam * g.x, b[k].y - lam * g.y);
+    }
+}
+
+// (p, q) <- projection onto |(p, q)_ij| <= w_ij of (r, s) + grad(u) / (8 lam);
+// (r, s) <- (p, q) + c ((p, q) - (p, q)_previous).
+template <typename R>
+__global__ void tv_dual(const C<R> *u, const R *w, C<R> *p, C<R> *q, C<R> *r, C<R> *s, int n, const double *lamp,
+                        double c) {
+    const double lam = *lamp;
+    const R step = lam > 0 ? (R)(1.0 / (8.0 * lam)) : R(0);
+    const R cc = (R)c;
+    GRID_LOOP(k, (long)n * n) {
+        const int i = (int)(k / n), j = (int)(k - (long)i * n);
+        const C<R> uk = u[k];
+        const C<R> gx = i < n - 1 ? csub<R>(u[k + n], uk) : mk<R>(0, 0);
+        const C<R> gy = j < n - 1 ? csub<R>(u[k + 1], uk) : mk<R>(0, 0);
+        C<R> pn = mk<R>(r[k].x + step * gx.x, r[k].y + step * gx.y);
+        C<R> qn = mk<R>(s[k].x + step * gy.x, s[k].y + step * gy.y);
+        const R wk = w ? w[k] : R(1);
+        if (wk > R(0)) {
+            const R mag = sqrt(pn.x * pn.x + pn.y * pn.y + qn.x * qn.x + qn.y * qn.y);
+            if (mag > wk) {
+                const R f = wk / mag;
+                pn = cscale<R>(pn, f);
+                qn = cscale<R>(qn, f);
+            }
+        } else {
+            pn = mk<R>(0, 0);
+            qn = mk<R>(0, 0);
+        }
+        const C<R> po = p[k], qo = q[k];
+        r[k] = mk<R>(pn.x + cc * (pn.x - po.x), pn.y + cc * (pn.y - po.y));
+        s[k] = mk<R>(qn.x + cc * (qn.x - qo.x), qn.y + cc * (qn.y - qo.y));
+        p[k] = pn;
+        q[k] = qn;
+    }
+}
+
+// r1 = b - lam gradT(p, q); z1 <- b - r1; x1 = r1 - z1 (Algorithm 1 steps 7-9, L1 = I).
+template <typename R>
+__global__ void tv_finish(const C<R> *b, const C<R> *p, const C<R> *q, C<R> *z1, C<R> *x1, int n, const double *lamp) {
+    const R lam = (R)*lamp;
+    GRID_LOOP(k, (long)n * n) {
+        const int i = (int)(k / n), j = (int)(k - (long)i * n);
+        const C<R> g = grad_adj_at<R>(p, q, i, j, n);
+        const C<R> bk = b[k];
+        const C<R> r1 = mk<R>(bk.x - lam * g.x, bk.y - lam * g.y);
+        const C<R> zn = csub<R>(bk, r1);
+        z1[k] = zn;
+        x1[k] = csub<R>(r1, zn);
+    }
+}
+
+// SLOT_F1 partials of f1 = sum_ij w_ij |(grad x)_ij|.
+template <typename R> __global__ void tv_norm_partials(const C<R> *x, const R *w, int n, double *partials) {
+    double acc = 0.0;
+    GRID_LOOP(k, (long)n * n) {
+        const int i = (int)(k / n), j = (int)(k - (long)i * n);
+        const C<R> xk = x[k];
+        const C<R> gx = i < n - 1 ? csub<R>(x[k + n], xk) : mk<R>(0, 0);
+        const C<R> gy = j < n - 1 ? csub<R>(x[k + 1], xk) : mk<R>(0, 0);
+        const double m = sqrt(abs2<R>(gx) + abs2<R>(gy));
+        acc += w ? (double)w[k] * m : m;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[SLOT_F1 * kRedBlocks + blockIdx.x] = t;
+}
+
+// slot <- sum_ij |(grad x)_ij|^2
+template <typename R> __global__ void tv_sum_mag2(const C<R> *x, int n, double *partials, int slot) {
+    double acc = 0.0;
+    GRID_LOOP(k, (long)n * n) {
+        const int i = (int)(k / n), j = (int)(k - (long)i * n);
+        const C<R> xk = x[k];
+        const C<R> gx = i < n - 1 ? csub<R>(x[k + n], xk) : mk<R>(0, 0);
+        const C<R> gy = j < n - 1 ? csub<R>(x[k + 1], xk) : mk<R>(0, 0);
+        acc += abs2<R>(gx) + abs2<R>(gy);
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[slot * kRedBlocks + blockIdx.x] = t;
+}
+
+// RWTV weights: w_ij = delta / (delta + |(grad x)_ij|).
+template <typename R> __global__ void tv_reweight(const C<R> *x, R *w, int n, double delta) {
+    GRID_LOOP(k, (long)n * n) {
+        const int i = (int)(k / n), j = (int)(k - (long)i * n);
+        const C<R> xk = x[k];
+        const C<R> gx = i < n - 1 ? csub<R>(x[k + n], xk) : mk<R>(0, 0);
+        const C<R> gy = j < n - 1 ? csub<R>(x[k + 1], xk) : mk<R>(0, 0);
+        w[k] = (R)(delta / (delta + sqrt(abs2<R>(gx) + abs2<R>(gy))));
+    }
+}
+
 // Reweighted l1 (Sec. 3.3): w_j = delta / (delta + |alpha_j|).
 template <typename R> __global__ void reweight_weights(const C<R> *alpha, R *w, long D, double delta) {
     GRID_LOOP(i, D) w[i] = (R)(delta / (delta + sqrt(abs2<R>(alpha[i]))));
@@ -599,15 +732,20 @@ static void cg_run(riop_plan *p, const void *b, void *x, int n_iter, double tol,
     *final_slot = cur;
 }
 
+// gamma = beta ||L1^dagger Phi^dagger y||_inf with L1 = Psi^dagger (SARA) or I (TV).
 template <typename R> static void gamma_run(riop_plan *p, const void *y_sorted_or_user, int user, double beta,
-                                            hipStream_t s, int which) {
+                                            hipStream_t s, int which, int prior = PRIOR_SARA) {
     ensure_work(p);
     SdmmWork &w = p->sd;
-    const long D = (long)p->q * p->n * p->n;
+    const long N = (long)p->n * p->n, D = (long)p->q * N;
     launch_grid<R>(p, y_sorted_or_user, user, s);
     launch_phi_fft_adjoint<R>(p, w.tmpN.ptr, s);
-    launch_psi_adj<R>(p, w.tmpN.ptr, w.w1.ptr, s);
-    VEC_LAUNCH(p, max_abs<R>, RB(), RT(), 0, s, w.w1.as<C<R>>(), D, w.partials.as<double>(), (int)SLOT_MAX);
+    if (prior == PRIOR_TV) {
+        VEC_LAUNCH(p, max_abs<R>, RB(), RT(), 0, s, w.tmpN.as<C<R>>(), N, w.partials.as<double>(), (int)SLOT_MAX);
+    } else {
+        launch_psi_adj<R>(p, w.tmpN.ptr, w.w1.ptr, s);
+        VEC_LAUNCH(p, max_abs<R>, RB(), RT(), 0, s, w.w1.as<C<R>>(), D, w.partials.as<double>(), (int)SLOT_MAX);
+    }
     VEC_LAUNCH(p, gamma_from_max, dim3(1), RT(), 0, s, (const double *)w.partials.as<double>(), (int)SLOT_MAX,
                        beta, w.scalars.as<double>(), which);
     RIOP_HIP(hipGetLastError());
@@ -616,10 +754,18 @@ template <typename R> static void gamma_run(riop_plan *p, const void *y_sorted_o
 // Algorithm 1, steps 1-3 (or a resumed state), penalty and data in plan order.
 template <typename R>
 static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, const void *x0,
-                      hipStream_t s) {
+                      hipStream_t s, int prior = PRIOR_SARA, int tv_inner = 0) {
     ensure_work(p);
     SdmmWork &w = p->sd;
-    const long N = (long)p->n * p->n, D = (long)p->q * N, M = (long)p->M;
+    const long N = (long)p->n * p->n, M = (long)p->M;
+    // Length of the l1 term's variables: q N coefficients (SARA) or N pixels (TV).
+    const long D = prior == PRIOR_TV ? N : (long)p->q * N;
+    if (prior == PRIOR_TV) {
+        for (DevBuf *b : {&w.tvb, &w.tvu, &w.tvp, &w.tvq, &w.tvr, &w.tvs}) b->reserve(cbytes(p) * (size_t)N);
+    }
+    if (w.prior != prior || w.tv_inner != tv_inner) ++w.epoch;
+    w.prior = prior;
+    w.tv_inner = tv_inner;
     const size_t cb = cbytes(p);
     double *sc = w.scalars.as<double>();
     // The history buffer only grows, so that its address (held by graphs
@@ -656,7 +802,7 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
     if (prm->gamma > 0) {
         VEC_LAUNCH(p, set_scalar, dim3(1), dim3(1), 0, s, sc, (int)SC_GAMMA, prm->gamma);
     } else {
-        gamma_run<R>(p, w.ysort.ptr, 0, prm->beta, s, (int)SC_GAMMA);
+        gamma_run<R>(p, w.ysort.ptr, 0, prm->beta, s, (int)SC_GAMMA, prior);
     }
     if (prm->resume) {
         RIOP_REQUIRE(x0 && prm->z1 && prm->z2 && prm->z3 && prm->rhs, RIOP_EINVAL,
@@ -681,8 +827,12 @@ static void sdmm_init(riop_plan *p, const void *y, double eps, const riop_sdmm_p
         launch_fill_zero<R>(w.z3loc.ptr, N, s);
         if (x0) {
             RIOP_HIP(hipMemcpyAsync(xh, x0, cb * N, hipMemcpyDeviceToDevice, s));
-            launch_psi_adj<R>(p, xh, w.w1.ptr, s);
-            launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+            if (prior == PRIOR_TV) {  // L1 = I: x1 = x0
+                RIOP_HIP(hipMemcpyAsync(w.x1.ptr, x0, cb * N, hipMemcpyDeviceToDevice, s));
+            } else {
+                launch_psi_adj<R>(p, xh, w.w1.ptr, s);
+                launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+            }
             // x2 = Phi^dagger Phi x0 cancels against the warm start: rhs = x1 + x0.
             phi_into_s2<R>(p, xh, s);
             VEC_LAUNCH(p, lin2<R>, RB(), RT(), 0, s, (const C<R> *)w.x1.as<C<R>>(), (const C<R> *)xh, R(1),
@@ -715,9 +865,34 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         // (rhs holds the sum less Phi^dagger Phi x).
         int rr_slot = SLOT_RR0;
         cg_run<R>(p, w.rhs.ptr, xh, w.n_cg, w.cg_tol, &rr_slot, s, plan_cg_work<R>(p), true);
-        // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
-        launch_psi_adj_prox<R>(p, xh, px, s);
-        launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+        if (w.prior == PRIOR_TV) {
+            // Steps 7-9, i = 1 with L1 = I: r1 = prox of gamma ||W grad .||_1 at
+            // xhat + z1 by fast gradient projection on the dual; x1 = r1 - z1.
+            const long N = (long)p->n * p->n;
+            const int n = p->n;
+            const R *tw = static_cast<const R *>(w.weights);
+            VEC_LAUNCH(p, tv_begin<R>, RB(), RT(), 0, s, (const C<R> *)xh, (const C<R> *)w.z1loc.as<C<R>>(),
+                       w.tvb.as<C<R>>(), w.tvp.as<C<R>>(), w.tvq.as<C<R>>(), w.tvr.as<C<R>>(), w.tvs.as<C<R>>(), N);
+            double tk = 1.0;
+            for (int k = 0; k < w.tv_inner; ++k) {
+                const double tn = (1.0 + std::sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
+                VEC_LAUNCH(p, tv_u<R>, RB(), RT(), 0, s, (const C<R> *)w.tvb.as<C<R>>(),
+                           (const C<R> *)w.tvr.as<C<R>>(), (const C<R> *)w.tvs.as<C<R>>(), w.tvu.as<C<R>>(), n,
+                           (const double *)(sc + SC_GAMMA));
+                VEC_LAUNCH(p, tv_dual<R>, RB(), RT(), 0, s, (const C<R> *)w.tvu.as<C<R>>(), tw, w.tvp.as<C<R>>(),
+                           w.tvq.as<C<R>>(), w.tvr.as<C<R>>(), w.tvs.as<C<R>>(), n, (const double *)(sc + SC_GAMMA),
+                           (tk - 1.0) / tn);
+                tk = tn;
+            }
+            VEC_LAUNCH(p, tv_finish<R>, RB(), RT(), 0, s, (const C<R> *)w.tvb.as<C<R>>(),
+                       (const C<R> *)w.tvp.as<C<R>>(), (const C<R> *)w.tvq.as<C<R>>(), w.z1loc.as<C<R>>(),
+                       w.x1.as<C<R>>(), n, (const double *)(sc + SC_GAMMA));
+            VEC_LAUNCH(p, tv_norm_partials<R>, RB(), RT(), 0, s, (const C<R> *)xh, tw, n, part);
+        } else {
+            // Steps 7-9, i = 1: soft threshold fused into Psi^dagger; x1 = Psi (r1 - z1).
+            launch_psi_adj_prox<R>(p, xh, px, s);
+            launch_psi<R>(p, w.w1.ptr, w.x1.ptr, s);
+        }
         // i = 2: projection onto the l2 ball around y; x2 = Phi^dagger (r2 - z2),
         // taken as Phi^dagger (r2 - z2 - Phi xhat) for the next warm start.
         phi_into_s2<R>(p, xh, s);
@@ -745,7 +920,8 @@ template <typename R> static void sdmm_step(riop_plan *p, int iters, hipStream_t
         // i = 3 and the next right-hand side.
         VEC_LAUNCH(p, prox3_rhs<R>, RB(), RT(), 0, s, (const C<R> *)xh, w.z3loc.as<C<R>>(), w.x1.as<C<R>>(),
                    w.tmpN.as<C<R>>(), w.rhs.as<C<R>>(), N);
-        VEC_LAUNCH(p, f1_partials, RB(), RT(), 0, s, (const double *)w.f1part.as<double>(), w.f1_count, part);
+        if (w.prior != PRIOR_TV)
+            VEC_LAUNCH(p, f1_partials, RB(), RT(), 0, s, (const double *)w.f1part.as<double>(), w.f1_count, part);
         VEC_LAUNCH(p, record_stats, dim3(1), RT(), 0, s, (const double *)part, sc, w.history.as<double>(),
                    w.hist_cap, rr_slot);
         RIOP_HIP(hipGetLastError());
@@ -763,7 +939,8 @@ static void sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, 
     const size_t cb = cbytes(p);
     double *sc = w.scalars.as<double>();
     if (x_out) RIOP_HIP(hipMemcpyAsync(x_out, w.xhat.ptr, cb * N, hipMemcpyDeviceToDevice, s));
-    if (prm && prm->z1) RIOP_HIP(hipMemcpyAsync(prm->z1, w.z1loc.ptr, cb * D, hipMemcpyDeviceToDevice, s));
+    const long D1 = w.prior == PRIOR_TV ? N : D;  // the l1 term's dual: q N (SARA) or N (TV)
+    if (prm && prm->z1) RIOP_HIP(hipMemcpyAsync(prm->z1, w.z1loc.ptr, cb * D1, hipMemcpyDeviceToDevice, s));
     if (prm && prm->z3) RIOP_HIP(hipMemcpyAsync(prm->z3, w.z3loc.ptr, cb * N, hipMemcpyDeviceToDevice, s));
     if (prm && prm->rhs) {  // b = rhs + Phi^dagger Phi xhat
         phi_adj_sorted<R>(p, w.s2.ptr, w.tmpN.ptr, s);
@@ -804,8 +981,8 @@ static void sdmm_finish(riop_plan *p, const riop_sdmm_params *prm, void *x_out, 
 
 template <typename R>
 static void sdmm_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, void *x_inout,
-                     riop_sdmm_stats *stats, hipStream_t s) {
-    sdmm_init<R>(p, y, eps, prm, x_inout, s);
+                     riop_sdmm_stats *stats, hipStream_t s, int prior = PRIOR_SARA, int tv_inner = 0) {
+    sdmm_init<R>(p, y, eps, prm, x_inout, s, prior, tv_inner);
     // Inputs holding NaN or Inf end the call before any iteration.
     try {
         report_nonfinite(p, s);
@@ -910,10 +1087,11 @@ static double slot_to_host(riop_plan *p, int slot, hipStream_t s) {
 template <typename R>
 static void reweighted_run(riop_plan *p, const void *y, double eps, const riop_sdmm_params *inner,
                            const riop_reweight_params *rw, void *x, void *weights_out, riop_sdmm_stats *stats,
-                           int32_t *passes_out, hipStream_t s) {
+                           int32_t *passes_out, hipStream_t s, int prior = PRIOR_SARA, int tv_inner = 0) {
     ensure_work(p);
     SdmmWork &w = p->sd;
-    const long N = (long)p->n * p->n, D = (long)p->q * N;
+    const long N = (long)p->n * p->n;
+    const long D = prior == PRIOR_TV ? N : (long)p->q * N;  // one weight per coefficient or per pixel
     const size_t cb = cbytes(p);
     w.rw_w.reserve(rbytes(p) * (size_t)D);
     w.xprev.reserve(cb * (size_t)N);
@@ -924,29 +1102,42 @@ static void reweighted_run(riop_plan *p, const void *y, double eps, const riop_s
     prm.history = nullptr;
     riop_sdmm_stats st{};
     double *part = w.partials.as<double>();
-    sdmm_run<R>(p, y, eps, &prm, x, &st, s);
+    sdmm_run<R>(p, y, eps, &prm, x, &st, s, prior, tv_inner);
     prm.gamma = st.gamma;
     int passes = 1;
     double delta = 0.0;
     for (int k = 0; k < rw->outer; ++k) {
-        // Weights from the current solution's coefficients.
-        launch_psi_adj<R>(p, x, w.w1.ptr, s);
-        if (k == 0) {
-            if (rw->delta0 > 0) {
-                delta = rw->delta0;
-            } else {
-                VEC_LAUNCH(p, sum_abs2<R>, RB(), RT(), 0, s, (const C<R> *)w.w1.as<C<R>>(), D, part, (int)SLOT_MAX);
+        // Weights from the current solution's coefficients (SARA) or gradient
+        // magnitudes (TV); delta_1 defaults to the RMS of the same quantity.
+        if (prior == PRIOR_TV) {
+            if (k == 0 && rw->delta0 <= 0) {
+                VEC_LAUNCH(p, tv_sum_mag2<R>, RB(), RT(), 0, s, (const C<R> *)x, p->n, part, (int)SLOT_MAX);
                 const double ms = slot_to_host(p, SLOT_MAX, s) / (double)D;
                 delta = ms > 0 ? std::sqrt(ms) : 1.0;
+            } else {
+                delta = k == 0 ? rw->delta0 : std::max(rw->rho * delta, rw->delta_min);
             }
+            VEC_LAUNCH(p, tv_reweight<R>, RB(), RT(), 0, s, (const C<R> *)x, w.rw_w.as<R>(), p->n, delta);
         } else {
-            delta = std::max(rw->rho * delta, rw->delta_min);
+            launch_psi_adj<R>(p, x, w.w1.ptr, s);
+            if (k == 0) {
+                if (rw->delta0 > 0) {
+                    delta = rw->delta0;
+                } else {
+                    VEC_LAUNCH(p, sum_abs2<R>, RB(), RT(), 0, s, (const C<R> *)w.w1.as<C<R>>(), D, part,
+                               (int)SLOT_MAX);
+                    const double ms = slot_to_host(p, SLOT_MAX, s) / (double)D;
+                    delta = ms > 0 ? std::sqrt(ms) : 1.0;
+                }
+            } else {
+                delta = std::max(rw->rho * delta, rw->delta_min);
+            }
+            VEC_LAUNCH(p, reweight_weights<R>, RB(), RT(), 0, s, (const C<R> *)w.w1.as<C<R>>(), w.rw_w.as<R>(),
+                       D, delta);
         }
-        VEC_LAUNCH(p, reweight_weights<R>, RB(), RT(), 0, s, (const C<R> *)w.w1.as<C<R>>(), w.rw_w.as<R>(), D,
-                   delta);
         RIOP_HIP(hipMemcpyAsync(w.xprev.ptr, x, cb * N, hipMemcpyDeviceToDevice, s));
         prm.weights = w.rw_w.ptr;
-        sdmm_run<R>(p, y, eps, &prm, x, &st, s);
+        sdmm_run<R>(p, y, eps, &prm, x, &st, s, prior, tv_inner);
         ++passes;
         if (rw->tol > 0) {
             VEC_LAUNCH(p, diff_norms<R>, RB(), RT(), 0, s, (const C<R> *)x, (const C<R> *)w.xprev.as<C<R>>(), N,
@@ -1170,6 +1361,42 @@ riop_status riop_sdmm(riop_plan *p, const void *y, double eps, const riop_sdmm_p
             sdmm_run<double>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
         else
             sdmm_run<float>(p, y, eps, prm, x_inout, stats, static_cast<hipStream_t>(stream));
+    });
+}
+
+riop_status riop_sdmm_tv(riop_plan *p, const void *y, double eps, const riop_sdmm_params *prm, int32_t n_inner,
+                         const riop_reweight_params *rw, void *x_inout, void *weights_out, riop_sdmm_stats *stats,
+                         int32_t *passes, void *stream) {
+    return guarded2([&] {
+        check_plan2(p);
+        RIOP_REQUIRE(prm, RIOP_EINVAL, "params is NULL");
+        RIOP_REQUIRE(y || p->M == 0, RIOP_EINVAL, "y is NULL");
+        RIOP_REQUIRE(eps > 0 && std::isfinite(eps), RIOP_EINVAL, "eps must be positive and finite");
+        RIOP_REQUIRE(prm->T >= 0 && prm->n_cg >= 0 && n_inner >= 0, RIOP_EINVAL, "T, n_cg and n_inner must be >= 0");
+        RIOP_REQUIRE(prm->gamma > 0 || prm->beta > 0, RIOP_EINVAL, "need gamma > 0 or beta > 0");
+        RIOP_REQUIRE(prm->cg_tol >= 0 && std::isfinite(prm->cg_tol), RIOP_EINVAL, "cg_tol must be finite and >= 0");
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        if (rw) {
+            RIOP_REQUIRE(x_inout, RIOP_EINVAL, "a reweighted run needs x_inout");
+            RIOP_REQUIRE(!prm->weights && !prm->resume && !prm->z1 && !prm->z2 && !prm->z3 && !prm->rhs &&
+                             !prm->history,
+                         RIOP_EINVAL, "the reweighted run owns the weights and state: weights, resume, state and "
+                                      "history pointers must be zero");
+            RIOP_REQUIRE(rw->outer >= 0 && rw->rho > 0 && rw->rho <= 1 && rw->delta_min >= 0 && rw->tol >= 0 &&
+                             std::isfinite(rw->delta0) && std::isfinite(rw->delta_min) && std::isfinite(rw->tol),
+                         RIOP_EINVAL, "reweighting: outer >= 0, 0 < rho <= 1, delta_min >= 0, tol >= 0, finite delta0");
+            if (p->prec == RIOP_F64)
+                reweighted_run<double>(p, y, eps, prm, rw, x_inout, weights_out, stats, passes, st, PRIOR_TV, n_inner);
+            else
+                reweighted_run<float>(p, y, eps, prm, rw, x_inout, weights_out, stats, passes, st, PRIOR_TV, n_inner);
+        } else {
+            RIOP_REQUIRE(!weights_out, RIOP_EINVAL, "weights_out is for reweighted runs");
+            if (p->prec == RIOP_F64)
+                sdmm_run<double>(p, y, eps, prm, x_inout, stats, st, PRIOR_TV, n_inner);
+            else
+                sdmm_run<float>(p, y, eps, prm, x_inout, stats, st, PRIOR_TV, n_inner);
+            if (passes) *passes = 1;
+        }
     });
 }
 

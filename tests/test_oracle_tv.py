@@ -129,3 +129,20 @@ def test_tv_sdmm_limit_is_optimal():
     assert np.linalg.norm(y - op.phi(xr)) <= eps * (1 + 1e-3)
     assert np.abs(np.imag(xh)).max() < 1e-4 and xr.min() > -1e-4
     assert tv.tv_norm(xr) == pytest.approx(fr, rel=2e-3)
+
+
+def test_rwtv_without_reweighting_is_tv():
+    from oracle import reweight
+    n, M, J, cfg = 8, 40, 6, 108
+    uv = W.coverage(M, W.rng(cfg, W.STREAM_UV))
+    op = nufft.Operator(n, uv, J)
+    y = W.random_complex(M, W.rng(cfg, 1)) * 0.1
+    xa, _, _, gam = tv.sdmm_tv(y, 0.5 * np.linalg.norm(y), op, T=6, n_cg=6, n_inner=10)
+    xb, passes, _ = reweight.sdmm_tv_reweighted(y, 0.5 * np.linalg.norm(y), op, T=6, n_cg=6, n_inner=10, outer=0)
+    assert passes == 1
+    np.testing.assert_array_equal(xa, xb)
+    # One pass: the weighted TV run from the first solution with the rule's weights.
+    xc, passes, info = reweight.sdmm_tv_reweighted(y, 0.5 * np.linalg.norm(y), op, T=6, n_cg=6, n_inner=10, outer=1)
+    w = tv.tv_weights(xa, reweight.first_delta(tv.magnitude(xa), 0.0))
+    xd, _, _, _ = tv.sdmm_tv(y, 0.5 * np.linalg.norm(y), op, T=6, n_cg=6, n_inner=10, gamma=gam, weights=w, x0=xa)
+    np.testing.assert_array_equal(xc, xd)

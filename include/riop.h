@@ -174,6 +174,23 @@ riop_status riop_plan_layout(const riop_plan *plan, int32_t *perm, uint32_t *cel
  *   x  device, n*n complex;  y  device, M complex (caller order).  x, y must not alias. */
 riop_status riop_phi(riop_plan *plan, const void *x, void *y, void *stream);
 
+/* Precomputed Gram operator G^T G (Sec. 4.5 and Sec. 7: storing G^T G lets
+ * the CG x-update skip the M-length vector G F D Z p of every iteration).
+ * riop_gram_build computes H = G^T G for the plan's coverage, with the plan's
+ * own kernel weights, and stores it banded: one K x K plane of the plan's real
+ * type per offset (da, db) of the half set (da = 0, 0 <= db < J, and
+ * 0 < da < J, |db| < J; J + (J - 1)(2J - 1) planes, 113 for J = 8), the other
+ * half by symmetry.  From then on every application of Phi^dagger Phi inside
+ * the plan (riop_apply_q, riop_cg, riop_cg_noalloc, the SDMM x-update) applies
+ * H to the oversampled spectrum instead of degridding and gridding; riop_phi
+ * and riop_phi_adj are unchanged.  Memory: planes x K^2 x (4 or 8) bytes
+ * (1.9 GB at 1024^2, J = 8, FP32), plus the same in doubles while building.
+ * It pays off when M is several times K^2; at M ~ K^2 degridding and
+ * gridding are faster.  Both synchronise; riop_gram_release frees H and
+ * returns the plan to degridding and gridding. */
+riop_status riop_gram_build(riop_plan *plan, void *stream);
+riop_status riop_gram_release(riop_plan *plan);
+
 /* x = Phi^dagger y, the exact adjoint of riop_phi (up to rounding).
  *   y  device, M complex (caller order);  x  device, n*n complex. */
 riop_status riop_phi_adj(riop_plan *plan, const void *y, void *x, void *stream);

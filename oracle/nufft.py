@@ -123,6 +123,18 @@ class Operator:
         """G^T w as a K x K grid (gridding alone)."""
         return real_matvec(self.G.T, w).reshape(self.K, self.K)
 
+    def gram(self) -> sp.csr_matrix:
+        """G^T G as a sparse K^2 x K^2 matrix (the precomputed Gram operator
+        proposed for the CG x-update, Sec. 4.5 and Sec. 7)."""
+        return (self.G.T @ self.G).tocsr()
+
+    def phi_adj_phi_gram(self, x: np.ndarray, H=None) -> np.ndarray:
+        """Phi^dagger Phi x with G^T G applied as the stored matrix H."""
+        H = self.gram() if H is None else H
+        grid = real_matvec(H, self.forward_grid(x).ravel()).reshape(self.K, self.K)
+        xp = np.fft.ifft2(grid) * self.K
+        return self.d[:, None] * self.d[None, :] * xp[np.ix_(self._rows, self._rows)]
+
     def degrid(self, grid: np.ndarray) -> np.ndarray:
         """G grid (degridding alone)."""
         return real_matvec(self.G, np.asarray(grid).ravel())

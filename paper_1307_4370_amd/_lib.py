@@ -23,7 +23,7 @@ STATUS = {0: "RIOP_OK", -1: "RIOP_EINVAL", -2: "RIOP_ESHAPE", -3: "RIOP_ENOMEM",
 
 # Entry points declared in include/riop.h (checked by the ABI test).
 EXPORTS = ("riop_plan_create", "riop_plan_destroy", "riop_plan_info", "riop_plan_layout",
-           "riop_plan_sync", "riop_device_bytes", "riop_noise_bound",
+           "riop_plan_sync", "riop_device_bytes", "riop_noise_bound", "riop_gram_build", "riop_gram_release",
            "riop_phi", "riop_phi_adj", "riop_phi_sorted", "riop_phi_adj_sorted",
            "riop_apply_q", "riop_psi_adj", "riop_psi", "riop_cg", "riop_cg_noalloc", "riop_gamma",
            "riop_sdmm", "riop_sdmm_reweighted", "riop_sdmm_blocks", "riop_sdmm_tv", "riop_batch_create", "riop_batch_sdmm", "riop_batch_plan", "riop_batch_tile",
@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.riop_cg.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(i32), vp]
         L.riop_cg_noalloc.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(dbl), ctypes.POINTER(i32), vp]
         L.riop_plan_sync.argtypes = [vp, vp]
+        L.riop_gram_build.argtypes = [vp, vp]
+        L.riop_gram_release.argtypes = [vp]
         L.riop_device_bytes.argtypes = []
         L.riop_noise_bound.argtypes = [i64, dbl]
         L.riop_gamma.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), vp]
@@ -267,6 +269,13 @@ class Plan:
         _check(lib().riop_cg(self._h, b.data_ptr(), x.data_ptr(), n_iter, float(tol), ctypes.byref(rr),
                              ctypes.byref(it), _stream(stream)))
         return (x, rr.value, it.value) if with_iters else (x, rr.value)
+
+    def gram_build(self, stream=None):
+        """Precompute G^T G; CG and Q then apply it instead of degridding and gridding."""
+        _check(lib().riop_gram_build(self._h, _stream(stream)))
+
+    def gram_release(self):
+        _check(lib().riop_gram_release(self._h))
 
     def sync(self, stream=None):
         """Synchronise; raises RiopError(RIOP_ENONFINITE) if an earlier call's input held NaN or Inf."""

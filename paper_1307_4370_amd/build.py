@@ -28,7 +28,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
-SOURCES = ["api.hip", "fft.hip", "gridding.hip", "sara.hip", "sdmm.hip", "batch.hip"]
+SOURCES = ["api.hip", "fft.hip", "gridding.hip", "gram.hip", "sara.hip", "sdmm.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:

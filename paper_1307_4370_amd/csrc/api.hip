@@ -150,7 +150,7 @@ TimedScope::~TimedScope() {
 
 static const char *kKindNames[KK_COUNT] = {"fft_fwd_col", "fft_fwd_row", "fft_adj_row", "fft_adj_col",
                                            "degrid",      "grid",        "grid_zero",   "psi_adj",
-                                           "psi",         "vector",      "grid_prox2"};
+                                           "psi",         "vector",      "grid_prox2",  "gram"};
 
 // ---------------------------------------------------------------------------
 // Kaiser-Bessel kernel on the host.
@@ -544,6 +544,27 @@ riop_status riop_plan_destroy(riop_plan *plan) {
     });
 }
 
+riop_status riop_gram_build(riop_plan *p, void *stream) {
+    return guarded([&] {
+        check_plan(p);
+        p->gram.release();
+        p->gram_offs.release();
+        p->gram_nplanes = 0;
+        gram_build_plan(p, S(stream));
+        mark_done(p, S(stream));
+    });
+}
+
+riop_status riop_gram_release(riop_plan *p) {
+    return guarded([&] {
+        check_plan(p);
+        if (p->done) RIOP_HIP(hipEventSynchronize(p->done));
+        p->gram.release();
+        p->gram_offs.release();
+        p->gram_nplanes = 0;
+    });
+}
+
 riop_status riop_plan_sync(riop_plan *p, void *stream) {
     return guarded([&] {
         check_plan(p);
@@ -581,7 +602,7 @@ riop_status riop_plan_info(const riop_plan *p, riop_info *info) {
         int64_t extra = 0;
         for (const DevBuf *b : {&p->sd.xhat, &p->sd.rhs, &p->sd.r, &p->sd.p, &p->sd.qp, &p->sd.tmpN, &p->sd.x1,
                                 &p->sd.z3loc, &p->sd.z1loc, &p->sd.w1, &p->sd.ysort, &p->sd.z2loc, &p->sd.s2,
-                                &p->sd.partials, &p->sd.scalars, &p->sd.history})
+                                &p->sd.partials, &p->sd.scalars, &p->sd.history, &p->gram, &p->gram_offs})
             extra += (int64_t)b->bytes;
         info->device_bytes = p->device_bytes + extra;
     });

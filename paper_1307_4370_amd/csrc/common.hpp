@@ -124,7 +124,7 @@ struct FftPlan {
 // Kernel kinds for event timing.
 enum KernelKind {
     KK_FFT_FWD_COL = 0, KK_FFT_FWD_ROW, KK_FFT_ADJ_ROW, KK_FFT_ADJ_COL,
-    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_GRID_PROX2, KK_COUNT
+    KK_DEGRID, KK_GRID, KK_GRID_ZERO, KK_PSI_ADJ, KK_PSI, KK_VECTOR, KK_GRID_PROX2, KK_GRAM, KK_COUNT
 };
 
 struct Timing {
@@ -229,6 +229,11 @@ struct riop_plan {
     riop::DevBuf ll;        // per-basis low-low scratch (analysis / synthesis)
     size_t ll_stride = 0;   // complex entries per basis in `ll`
 
+    // Precomputed Gram operator G^T G (optional): one K x K plane of the
+    // plan's real type per offset of the half set, and the offsets (int2).
+    riop::DevBuf gram, gram_offs;
+    int gram_nplanes = 0;
+
     riop::SdmmWork sd;
     riop::Timing timing;
     int64_t device_bytes = 0;
@@ -285,6 +290,10 @@ void check_grid_lds(riop_plan *p);
 // Complex cells of one tile's gridding halo slot.
 inline int grid_halo_cells(int T, int J) { return T * (J - 1) + (J - 1) * (T + J - 1); }
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
+// Precomputed G^T G: planes per offset for width J, build (synchronises) and apply.
+int gram_planes(int J);
+void gram_build_plan(riop_plan *p, hipStream_t st);
+template <typename R> void launch_gram_apply(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
 // Adds the gridding halos into `grid` (needed only where the adjoint FFT does
 // not add them while loading; see launch_phi_fft_adjoint).
 template <typename R> void launch_grid_merge(riop_plan *p, void *grid, hipStream_t st);

@@ -1053,8 +1053,13 @@ void launch_grid_prox2(riop_plan *p, const void *s, void *z2, const void *y, con
     launch_tiles<R>(p, nullptr, 0, p->grid.ptr, st, &q);
 }
 
-// out_grid = G^T G in_grid: degridding into plan-order scratch, then gridding.
+// out_grid = G^T G in_grid: the precomputed planes when the plan holds them,
+// else degridding into plan-order scratch, then gridding.
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st) {
+    if (p->gram.ptr) {
+        launch_gram_apply<R>(p, in_grid, out_grid, st);
+        return;
+    }
     launch_degrid_from<R>(p, in_grid, p->vis.ptr, 0, st);
     launch_tiles<R>(p, p->vis.ptr, 0, out_grid, st);
 }

@@ -205,3 +205,25 @@ def test_direct_points_is_the_direct_sum_of_a_sparse_image():
     uv = W.coverage(M, W.rng(8, 2))
     np.testing.assert_allclose(nufft.direct_points(pix, amps, uv, n, chunk=64), nufft.direct(x, uv),
                                rtol=0, atol=1e-13)
+
+
+def test_gram_matrix_is_gt_g():
+    """The stored Gram operator equals applying G then G^T, and has the band
+    structure the library stores: nonzero only for offsets |da|, |db| < J."""
+    n, M, J = 16, 900, 6
+    uv = W.coverage(M, W.rng(9, 1))
+    op = nufft.Operator(n, uv, J)
+    H = op.gram()
+    v = W.random_complex(op.K * op.K, W.rng(9, 2))
+    a = nufft.real_matvec(H, v)
+    b = nufft.real_matvec(op.G.T, nufft.real_matvec(op.G, v))
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+    x = W.random_complex((n, n), W.rng(9, 3))
+    q1 = op.phi_adj_phi_gram(x, H)
+    q2 = op.phi_adj(op.phi(x))
+    assert np.linalg.norm(q1 - q2) <= 1e-13 * np.linalg.norm(q2)
+    rows, cols = H.nonzero()
+    K = op.K
+    da = np.abs(((cols // K - rows // K) + K // 2) % K - K // 2)
+    db = np.abs(((cols % K - rows % K) + K // 2) % K - K // 2)
+    assert da.max() < J and db.max() < J

@@ -24,7 +24,11 @@ per-kernel times and the roofline of the dominant kernel come from a separate
 short run with HIP events on the library's stream.
 
 Also reported: SDMM iterations/s, the same in plain FP64, stand-alone
-Phi + Phi^dagger pair throughput, and the CPU oracle on a bounded sample.
+Phi + Phi^dagger pair throughput, a measured device-copy ceiling beside the
+8 TB/s peak, the FP32 path's errors against FP64 (this workload) and against
+the oracle (64^2), the 64^2 and 256^2 throughputs, Q applied through the
+stored G^T G against degridding + gridding, and the CPU oracle on a bounded
+pair (one core and all cores, per pair and per SDMM iteration).
 """
 from __future__ import annotations
 
@@ -125,7 +129,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind: str, n: int, M: int, cbytes: int):
+def algorithmic_bytes(kind: str, n: int, M: int, cbytes: int, J: int = 8):
     """Bytes the method must move per launch of one kernel kind.
 
     N = n^2 pixels, grid K^2 = 4N cells; complex = cbytes, (u, v) = cbytes.
@@ -136,48 +140,245 @@ def algorithmic_bytes(kind: str, n: int, M: int, cbytes: int):
       degrid:      read the grid 4N + (u, v) M, write y M            -> 4N + 2M
       grid:        read (u, v) M + values M, write the grid 4N       -> 4N + 2M
       grid_zero:   write the grid 4N
+      gram:        read the J + (J-1)(2J-1) real planes of G^T G (half a
+                   complex each per cell), read the grid 4N, write 4N
     """
     N = n * n
-    table = {"fft_fwd_col": 3 * N, "fft_fwd_row": 6 * N, "fft_adj_row": 6 * N, "fft_adj_col": 3 * N,
+    planes = J + (J - 1) * (2 * J - 1)
+    table = {"gram": 4 * N * 2 + 4 * N * planes / 2, "fft_fwd_col": 3 * N, "fft_fwd_row": 6 * N, "fft_adj_row": 6 * N, "fft_adj_col": 3 * N,
              "degrid": 4 * N + 2 * M, "grid": 4 * N + 2 * M, "grid_zero": 4 * N}
     return table[kind] * cbytes if kind in table else None
 
 
-def cpu_baseline(n, J, uv, x_true, sample_m=262144, pairs=2):
-    """FP64 oracle Phi + Phi^dagger on the host, bounded sample.
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The grid FFTs run at full size; the interpolation (G, G^T) runs on the first
-    ``sample_m`` visibilities and its time is scaled by M / sample_m, since its
-    cost is linear in M.  Building G (once per coverage) is not timed.
-    """
+
+def _oracle_pair_time(args):
+    """One oracle Phi + Phi^dagger pair on the given visibilities, best of
+    `pairs`: (seconds in the full-size grid FFTs, seconds in the interpolation
+    G then G^T).  Building G is not timed."""
+    n, J, uv, x, pairs = args
     import numpy as np
     from oracle import nufft
-    M = len(uv)
-    t0 = time.perf_counter()
-    op = nufft.Operator(n, uv[:sample_m], J)
-    t_build = time.perf_counter() - t0
-    x = x_true.astype(np.complex128)
-    t_fft = t_g = 0.0
+    op = nufft.Operator(n, uv, J)
+    t_fft = t_int = math.inf
     for _ in range(pairs):
         t0 = time.perf_counter()
         X = op.forward_grid(x)
         t1 = time.perf_counter()
-        y = op.degrid(X)
+        grid = op.grid_adj(op.degrid(X))
         t2 = time.perf_counter()
-        grid = op.grid_adj(y)
+        np.fft.ifft2(grid)
         t3 = time.perf_counter()
-        xa = np.fft.ifft2(grid)[: n, : n]
-        t4 = time.perf_counter()
-        t_fft += (t1 - t0) + (t4 - t3)
-        t_g += (t2 - t1) + (t3 - t2)
-    per_pair = (t_fft + t_g * (M / sample_m)) / pairs
+        t_fft = min(t_fft, (t1 - t0) + (t3 - t2))
+        t_int = min(t_int, t2 - t1)
+    return t_fft, t_int
+
+
+def cpu_baseline(n, J, L, uv, x_true, ncg, share=4, pairs=2):
+    """The FP64 oracle on the host, per Phi/Phi^dagger pair and per SDMM
+    iteration of the 1024^2 workload, from a bounded sample.
+
+    One core (the oracle as it is: numpy's FFT and scipy's sparse products run
+    on one thread): a pair with the full-size 2048^2 FFTs and the
+    interpolation (G, G^T) on the first M / `share` visibilities, the
+    interpolation time scaled by `share` (its cost is linear in M apart from
+    G^T's grid-sized part, a few per cent that the scaling counts `share`
+    times); and one Psi^dagger / Psi pair of the 9-basis dictionary.  An SDMM
+    iteration is taken as (n_cg + 2) pairs, as the method counts them, plus the
+    Psi pair (the prox and vector steps are small against these).  All cores
+    (capped at 16): the M visibilities split into one share per core, one
+    oracle process per share, all timed together, each with the full-size
+    FFTs; the pair time is the slowest share's, unscaled (summing the shares'
+    grids is not counted).
+    """
+    import numpy as np
+    from oracle import wavelets
+    M = len(uv)
+    m = M // share
+    x = x_true.astype(np.complex128)
+    t_fft, t_int = _oracle_pair_time((n, J, uv[:m], x, pairs))
+    per_pair_1 = t_fft + t_int * (M / m)
+    sara = wavelets.Sara(n, L)
+    t0 = time.perf_counter()
+    sara.psi(sara.psi_adj(x))
+    t_psi = time.perf_counter() - t0
+    per_iter_1 = (ncg + 2) * per_pair_1 + t_psi
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = min(avail, 16)
+    all_cores = None
+    if cores > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        shares = np.array_split(uv, cores)
+        with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+            per = max(tf + ti for tf, ti in ex.map(_oracle_pair_time, [(n, J, sh, x, 1) for sh in shares]))
+        all_cores = {"cores": cores, "visibilities_per_s": M / per, "seconds_per_pair": per,
+                     "sdmm_iters_per_s": 1.0 / ((ncg + 2) * per + t_psi),
+                     "note": "the M visibilities split over one oracle process per core, each with the "
+                             "full-size FFTs; grid sum and Psi pair not split"}
     return {
-        "value": M / per_pair, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{pairs} Phi+Phi^dagger pairs of the FP64 oracle on the 1024^2 workload: full-size "
-                   f"2048^2 FFTs, interpolation on {sample_m} of {M} visibilities scaled by M/{sample_m}; "
-                   f"G build ({t_build:.1f} s) not timed; numpy/scipy single-threaded"),
-        "seconds_per_pair": per_pair,
+        "value": M / per_pair_1, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 oracle pair on the 1024^2 workload: full-size 2048^2 FFTs, interpolation on "
+                   f"{m} of {M} visibilities scaled by {M / m:g} (G build not timed), best of {pairs}; "
+                   f"plus one 9-basis Psi pair; SDMM iteration = {ncg + 2} pairs + the Psi pair"),
+        "seconds_per_pair": per_pair_1,
+        "seconds_fft_per_pair": t_fft,
+        "seconds_psi_pair": t_psi,
+        "seconds_per_sdmm_iteration": per_iter_1,
+        "sdmm_iters_per_s": 1.0 / per_iter_1,
+        "all_cores": all_cores,
+        "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(), "cpus_available": avail,
     }
+
+
+def copy_ceiling(dev, mib=1024, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time)."""
+    import torch
+    nb = mib * 2 ** 20
+    src = torch.empty(nb, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+    del src, dst
+    return 2 * nb / dt / 1e9
+
+
+def small_workloads(dev, steps=20):
+    """Throughput of the 64^2 (M = 2048, J = 6) and 256^2 (M = 131072, J = 8)
+    workloads: SDMM iterations/s with n_cg = 16 and Phi + Phi^dagger pairs/s,
+    FP32 and FP64, as stream launches (inputs resident)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1307_4370_amd import Plan
+    out = {}
+    for c in (W.C1, W.C2):
+        x_true, uv = W.config_inputs(c)
+        row = {}
+        for prec in ("f32", "f64"):
+            rd = torch.float32 if prec == "f32" else torch.float64
+            cd = torch.complex64 if prec == "f32" else torch.complex128
+            plan = Plan(c.n, torch.tensor(uv, device=dev).to(rd), J=c.J, levels=c.levels, prec=prec)
+            xd = torch.tensor(x_true, device=dev).to(cd)
+            y = plan.phi(xd)
+            eps = 0.05 * float(torch.linalg.vector_norm(y))
+            plan.sdmm(y, eps, T=2, n_cg=c.n_cg)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            plan.sdmm(y, eps, T=steps, n_cg=c.n_cg)
+            torch.cuda.synchronize()
+            it_s = steps / (time.perf_counter() - a)
+            for _ in range(3):
+                plan.phi_adj(plan.phi(xd, y, sorted=True), sorted=True)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(50):
+                plan.phi_adj(plan.phi(xd, y, sorted=True), sorted=True)
+            torch.cuda.synchronize()
+            pair_s = 50 / (time.perf_counter() - a)
+            row[prec] = {"sdmm_iters_per_s": round(it_s, 2), "pairs_per_s": round(pair_s, 1),
+                         "visibilities_per_s": c.M * pair_s}
+            del plan
+        out[c.name] = {"n": c.n, "M": c.M, "J": c.J, **row}
+    log(f"small workloads: {out}")
+    return out
+
+
+def gram_crossover(dev):
+    """Q = Phi^dagger Phi + 2I with the stored G^T G against degridding and
+    gridding, FP32, J = 8: where M >> K^2 (256^2, M = 8388608) and at the
+    benchmark's M = K^2 (1024^2, M = 4194304)."""
+    import torch
+
+    import workloads as W
+    from paper_1307_4370_amd import Plan
+    rows = []
+    for n, M in ((256, 8388608), (1024, 4194304)):
+        uv = W.coverage(M, W.rng(700, n))
+        plan = Plan(n, torch.tensor(uv, device=dev).float(), J=8, levels=1, dict_mask=1, prec="f32")
+        x = torch.ones(n, n, dtype=torch.complex64, device=dev)
+
+        def q_us(reps=10):
+            for _ in range(3):
+                plan.apply_q(x)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(reps):
+                plan.apply_q(x)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - a) * 1e6 / reps
+
+        plain = q_us()
+        a = time.perf_counter()
+        plan.gram_build()
+        torch.cuda.synchronize()
+        build = time.perf_counter() - a
+        gram = q_us()
+        rows.append({"n": n, "M": M, "K2": (2 * n) ** 2, "us_per_Q_degrid_grid": round(plain, 1),
+                     "us_per_Q_stored_gram": round(gram, 1), "build_s": round(build, 3),
+                     "plan_device_GB": round(plan.info()["device_bytes"] / 1e9, 3)})
+        del plan
+        torch.cuda.empty_cache()
+    log(f"gram crossover: {rows}")
+    return rows
+
+
+def s1_errors(xa, sta, ha, xb, stb, hb, T):
+    """Relative errors of result a against reference b: the iterate (L2), nu,
+    gamma and f1 after the last iteration."""
+    import torch
+    xr = float(torch.linalg.vector_norm(xa.to(xb.dtype) - xb) / torch.linalg.vector_norm(xb))
+
+    def r(a, b):
+        return abs(a - b) / abs(b) if b else abs(a - b)
+    return {"iterations": T, "xhat_rel_l2": xr, "nu_rel": r(sta["nu"], stb["nu"]),
+            "gamma_rel": r(sta["gamma"], stb["gamma"]), "f1_rel": r(ha[-1][0], hb[-1][0])}
+
+
+def s1_vs_oracle(dev, T=20):
+    """The FP32 GPU path against the FP64 oracle on the 64^2 workload (M = 2048,
+    J = 6, 3 levels, n_cg = 16), T iterations from zero, both on the FP32-rounded
+    (u, v) and y so that only the arithmetic differs."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import nufft, sdmm as osdmm, wavelets
+    from paper_1307_4370_amd import Plan
+    c = W.C1
+    x_true, uv = W.config_inputs(c)
+    uv = uv.astype(np.float32).astype(np.float64)
+    op = nufft.Operator(c.n, uv, c.J)
+    y0 = op.phi(x_true)
+    sig = osdmm.noise_sigma(y0, c.isnr_db)
+    y = (y0 + sig * W.unit_complex_noise(c.M, W.rng(c.cfg, W.STREAM_NOISE))).astype(np.complex64)
+    eps = osdmm.noise_bound(c.M, sig)
+    xo, _, hist, gam = osdmm.sdmm(y.astype(np.complex128), eps, op, wavelets.Sara(c.n, c.levels), T, c.n_cg)
+    plan = Plan(c.n, torch.tensor(uv, device=dev).float(), J=c.J, levels=c.levels, prec="f32")
+    xg, st, gh, _ = plan.sdmm(torch.tensor(y, device=dev), eps, T=T, n_cg=c.n_cg)
+    torch.cuda.synchronize()
+    ref_st = {"nu": hist[-1]["nu"], "gamma": gam}
+    out = s1_errors(xg, st, gh, torch.tensor(xo, device=dev), ref_st, [[hist[-1]["f1"]]], T)
+    del plan
+    return out
 
 
 def batch_vs_plain(steps, ncg, dev):
@@ -263,6 +464,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (S2) vs per-channel comparison")
     ap.add_argument("--batch-steps", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the copy ceiling, the 64^2 / 256^2 throughputs and the Gram comparison")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the run, copy this many MiB device to device (counter calibration)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -388,12 +591,14 @@ def main():
     del ybuf
 
     fp64 = None
+    s1 = {}
     if not args.no_fp64:
         plan64, xd64, y64, eps64 = setup("f64")
         x64, st64, _, state64 = plan64.sdmm(y64, eps64, T=1, n_cg=ncg)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        plan64.sdmm(y64, eps64, T=args.fp64_steps, n_cg=ncg, gamma=st64["gamma"], x0=x64, state=state64)
+        x64, st64, h64, state64 = plan64.sdmm(y64, eps64, T=args.fp64_steps, n_cg=ncg, gamma=st64["gamma"],
+                                              x0=x64, state=state64)
         torch.cuda.synchronize()
         ms64 = (time.perf_counter() - a) * 1e3 / args.fp64_steps
         yb64 = torch.empty(M, dtype=torch.complex128, device=dev)
@@ -401,7 +606,15 @@ def main():
                 "visibilities_per_s": M * pairs_per_step / (ms64 * 1e-3),
                 "pair_visibilities_per_s": pair_rate(plan64, xd64, yb64, False, max(2, args.pairs // 4))}
         log(f"fp64: {fp64}")
-        del plan64, yb64
+        # FP32 against FP64 on this workload: the same measured data (the FP64
+        # y rounded to FP32), each path from zero for 1 + fp64_steps iterations
+        # with its own gamma.
+        T1 = 1 + args.fp64_steps
+        x32, st32, h32, _ = plan.sdmm(y64.to(torch.complex64), eps64, T=T1, n_cg=ncg)
+        torch.cuda.synchronize()
+        s1["fp32_vs_fp64_1024"] = s1_errors(x32, st32, h32, x64, st64, h64, T1)
+        log(f"S1 1024^2: {s1['fp32_vs_fp64_1024']}")
+        del plan64, yb64, x32
 
     if args.copy_probe:
         nb = args.copy_probe * 2 ** 20
@@ -413,6 +626,16 @@ def main():
         log(f"copy probe: {args.copy_probe} MiB x 3")
         del src, dst
 
+    extras = {}
+    if not args.no_extras:
+        extras["copy_GBs"] = copy_ceiling(dev)
+        log(f"device copy: {extras['copy_GBs']:.1f} GB/s")
+        extras["small"] = small_workloads(dev)
+        extras["gram"] = gram_crossover(dev)
+    if "copy_GBs" in extras:
+        roofline["copy_ceiling_GBs"] = round(extras["copy_GBs"], 1)
+        roofline["frac_of_copy"] = round(ach / extras["copy_GBs"], 4)
+
     s2 = None
     if not args.no_batch:
         s2 = batch_vs_plain(args.batch_steps, ncg, dev)
@@ -420,8 +643,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(n, J, uv, x_true)
-        log(f"cpu: {cpu['value']:.4g} vis/s")
+        cpu = cpu_baseline(n, J, L, uv, x_true, ncg)
+        log(f"cpu: {cpu}")
+        s1["fp32_vs_oracle_64"] = s1_vs_oracle(dev)
+        log(f"S1 64^2: {s1['fp32_vs_oracle_64']}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "visibilities/s", "n_gpus": 1,
@@ -443,6 +668,9 @@ def main():
         "roofline": roofline,
         "kernels": kern,
         "cpu_baseline": cpu,
+        "s1_errors": s1 or None,
+        "small_workloads": extras.get("small"),
+        "gram_vs_degrid_grid": extras.get("gram"),
         "batch_s2": s2,
         "final_nu": st["nu"],
     }

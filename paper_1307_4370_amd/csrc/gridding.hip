@@ -434,22 +434,30 @@ template <typename R> struct TileArgs {
 };
 
 // Own cells of tile t to the grid, the rest of its region to its halo slot.
+// T is a power of two (shifts and masks); the bottom strip's row is found by
+// a single-precision reciprocal, exact here: cell index and strip width are
+// small integers, so (c + 1/2) / W stays at least 1 / (2 W) away from the
+// integers.
 template <typename R, int J>
 __device__ inline void store_region(const TileArgs<R> &a, const double *tre, const double *tim, int t, int tid,
                                     int nthreads) {
-    const int T = a.T, K = a.K, RS = region_stride(T, J);
+    const int T = a.T, K = a.K, RS = region_stride(T, J), lt = __builtin_ctz(T);
     const int ta = (t / a.tps) * T, tb = (t % a.tps) * T;
+    C<R> *gbase = a.grid + (int64_t)ta * K + tb;
     for (int c = tid; c < T * T; c += nthreads) {
-        const int r = c / T, col = c - r * T;
-        a.grid[(int64_t)(ta + r) * K + tb + col] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+        const int r = c >> lt, col = c & (T - 1);
+        gbase[(int64_t)r * K + col] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
     }
     C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
     for (int c = tid; c < T * (J - 1); c += nthreads) {  // right strip
         const int r = c / (J - 1), col = T + c - r * (J - 1);
         halo[c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
     }
-    for (int c = tid; c < (J - 1) * (T + J - 1); c += nthreads) {  // bottom strip with the corner
-        const int r = T + c / (T + J - 1), col = c % (T + J - 1);
+    const int W = T + J - 1;
+    const float inv = 1.0f / (float)W;
+    for (int c = tid; c < (J - 1) * W; c += nthreads) {  // bottom strip with the corner
+        const int q = (int)(((float)c + 0.5f) * inv);
+        const int r = T + q, col = c - q * W;
         halo[T * (J - 1) + c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
     }
 }
@@ -512,10 +520,10 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     const WorkUnit wk = a.order[blockIdx.x];
     const int t = wk.tile, v0 = wk.start, total = wk.count;
     if (total == 0) {  // an empty tile: zeros for its cells and its halo slot, no region
-        const int ta0 = (t / tps) * T, tb0 = (t % tps) * T;
+        const int ta0 = (t / tps) * T, tb0 = (t % tps) * T, lt = __builtin_ctz(T);
         for (int c = tid; c < T * T; c += kThreads) {
-            const int r = c / T;
-            a.grid[(int64_t)(ta0 + r) * K + tb0 + c - r * T] = mk<R>(0, 0);
+            const int r = c >> lt;
+            a.grid[(int64_t)(ta0 + r) * K + tb0 + (c & (T - 1))] = mk<R>(0, 0);
         }
         C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
         for (int c = tid; c < halo_cells(T, J); c += kThreads) halo[c] = mk<R>(0, 0);
@@ -639,15 +647,14 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
             }
 #pragma unroll
             for (int i = 0; i < J; ++i) wuv[i * SR + lane] = mk<R>(wu_[i] * val.x, wu_[i] * val.y);
-            // Column weights at rows db .. db + J - 1, zeros in the other rows.
+            // Column weights at rows db .. db + J - 1, zeros in the other
+            // rows: all rows cleared at fixed offsets, then the weights
+            // written over them (one wavefront's LDS writes land in order).
 #pragma unroll
-            for (int c = 0; c < NC - J; ++c) {
-                int row = db + J + c;
-                row = row >= NC ? row - NC : row;
-                wv[row * SR + lane] = R(0);
-            }
+            for (int r = 0; r < NC; ++r) wv[r * SR + lane] = R(0);
+            R *wcol = wv + db * SR + lane;
 #pragma unroll
-            for (int j = 0; j < J; ++j) wv[(db + j) * SR + lane] = wv_[j];
+            for (int j = 0; j < J; ++j) wcol[j * SR] = wv_[j];
         }
         // Run starts: entries whose window row or column block differs from
         // the previous entry's (lane 0 compares with the open run).
@@ -661,29 +668,58 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
             // Groups of 4 entries; a group holding run starts is split into
             // products over the entries of each run (B masked by entry).
             const float *wuf = reinterpret_cast<const float *>(wuv);
+            if (nlive == 64) {
 #pragma unroll
-            for (int g = 0; g < 16; ++g) {
-                const float av = wuf[abase + 8 * g];
-                const float bv = wv[bbase + 4 * g];
-                const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;
-                if (__builtin_expect(s4 == 0, 1)) {
-                    dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc, 0, 0, 0);
-                } else {
-                    unsigned m = s4;
-                    int lo = 0;
-                    while (m) {
-                        const int b = __builtin_ctz(m);
-                        m &= m - 1;
-                        if (b > lo) {
-                            const float bm = (mk_ >= lo && mk_ < b) ? bv : 0.f;
-                            dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                for (int g = 0; g < 16; ++g) {
+                    const float av = wuf[abase + 8 * g];
+                    const float bv = wv[bbase + 4 * g];
+                    const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;
+                    if (__builtin_expect(s4 == 0, 1)) {
+                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc, 0, 0, 0);
+                    } else {
+                        unsigned m = s4;
+                        int lo = 0;
+                        while (m) {
+                            const int b = __builtin_ctz(m);
+                            m &= m - 1;
+                            if (b > lo) {
+                                const float bm = (mk_ >= lo && mk_ < b) ? bv : 0.f;
+                                dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                            }
+                            if (cur >= 0) close_run_mf(cur);
+                            cur = __builtin_amdgcn_readlane(pos, 4 * g + b);
+                            lo = b;
                         }
-                        if (cur >= 0) close_run_mf(cur);
-                        cur = __builtin_amdgcn_readlane(pos, 4 * g + b);
-                        lo = b;
+                        const float bm = mk_ >= lo ? bv : 0.f;
+                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
                     }
-                    const float bm = mk_ >= lo ? bv : 0.f;
-                    dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                }
+            } else {  // a partial slice: its groups past the last live entry are all zero
+                const int ng = (nlive + 3) >> 2;
+#pragma unroll 1
+                for (int g = 0; g < ng; ++g) {
+                    const float av = wuf[abase + 8 * g];
+                    const float bv = wv[bbase + 4 * g];
+                    const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;
+                    if (__builtin_expect(s4 == 0, 1)) {
+                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc, 0, 0, 0);
+                    } else {
+                        unsigned m = s4;
+                        int lo = 0;
+                        while (m) {
+                            const int b = __builtin_ctz(m);
+                            m &= m - 1;
+                            if (b > lo) {
+                                const float bm = (mk_ >= lo && mk_ < b) ? bv : 0.f;
+                                dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                            }
+                            if (cur >= 0) close_run_mf(cur);
+                            cur = __builtin_amdgcn_readlane(pos, 4 * g + b);
+                            lo = b;
+                        }
+                        const float bm = mk_ >= lo ? bv : 0.f;
+                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                    }
                 }
             }
         } else {

@@ -105,9 +105,9 @@ def traffic_summary(fetch_dir, write_dir, probe_mib):
              "Commands (repository root on the MI355X host, one counter pass each):\n", "```",
              "cd /tmp && export TMPDIR=/tmp",
              f"timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o t -- "
-             f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --no-batch --copy-probe {probe_mib}",
+             f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --no-batch --no-extras --copy-probe {probe_mib}",
              f"timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o t -- "
-             f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --no-batch --copy-probe {probe_mib}",
+             f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --no-batch --no-extras --copy-probe {probe_mib}",
              f"python3 $REPO/bench.py --traffic-summary $REPO/gpurun_out/pmc_fetch $REPO/gpurun_out/pmc_write "
              f"--copy-probe {probe_mib}", "```\n",
              f"Calibration: a plain {probe_mib} MiB device copy; its counter reading is scaled to exactly "

@@ -250,8 +250,8 @@ void build_kernel_tables(riop_plan *p) {
     std::vector<double> d(n);
     for (int i = 0; i < n; ++i) d[i] = 1.0 / kb_phihat(i - n / 2, J, K, beta, i0b);
     const size_t rb = rbytes(p);
-    p->kcoef_host = coef;
-    // Compact copy [pair][even/odd][D/2 + 1] for kernels that stage it in LDS.
+    // Device table [pair][even/odd][D/2 + 1] in the plan's type, read by the
+    // gridding, degridding and Gram kernels.
     const int KS = D / 2 + 1;
     std::vector<double> compact((size_t)(J / 2) * 2 * KS, 0.0);
     for (int jp = 0; jp < J / 2; ++jp)
@@ -264,14 +264,11 @@ void build_kernel_tables(riop_plan *p) {
         std::vector<float> c32(compact.begin(), compact.end());
         RIOP_HIP(hipMemcpy(p->kcoef_compact.ptr, c32.data(), rb * c32.size(), hipMemcpyHostToDevice));
     }
-    p->kcoef.alloc(rb * coef.size());
     p->deapod.alloc(rb * n);
     if (p->prec == RIOP_F64) {
-        RIOP_HIP(hipMemcpy(p->kcoef.ptr, coef.data(), rb * coef.size(), hipMemcpyHostToDevice));
         RIOP_HIP(hipMemcpy(p->deapod.ptr, d.data(), rb * n, hipMemcpyHostToDevice));
     } else {
-        std::vector<float> c32(coef.begin(), coef.end()), d32(d.begin(), d.end());
-        RIOP_HIP(hipMemcpy(p->kcoef.ptr, c32.data(), rb * c32.size(), hipMemcpyHostToDevice));
+        std::vector<float> d32(d.begin(), d.end());
         RIOP_HIP(hipMemcpy(p->deapod.ptr, d32.data(), rb * n, hipMemcpyHostToDevice));
     }
 }
@@ -518,7 +515,7 @@ riop_status riop_plan_create(const riop_desc *desc, const void *uv, void *stream
         RIOP_HIP(hipStreamSynchronize(s));
         p->device_bytes = 0;
         for (const DevBuf *b : {&p->perm, &p->cell, &p->frac, &p->tile_start, &p->units, &p->cell_start,
-                                &p->tile_order, &p->halo, &p->kcoef, &p->kcoef_compact, &p->deapod,
+                                &p->tile_order, &p->halo, &p->kcoef_compact, &p->deapod,
                                 &p->fft.twiddle, &p->tmp, &p->grid, &p->grid2, &p->vis, &p->img, &p->filters, &p->ll})
             p->device_bytes += (int64_t)b->bytes;
     });

@@ -40,7 +40,23 @@ namespace riop {
 static const int kTiles[4] = {8, 16, 32, 64};
 
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int64_t, int, int>, std::pair<int, std::vector<double>>> g_tune_cache;
+// Keyed by (n, M, J, precision, hash of the coverage): channels of one shape
+// but different (u, v) get their own tile choice.
+static std::map<std::tuple<int, int64_t, int, int, uint64_t>, std::pair<int, std::vector<double>>> g_tune_cache;
+
+// 64-bit FNV-1a hash of the coverage's bytes (copied to the host once per
+// tuned channel; the timing runs that follow cost far more).
+static uint64_t coverage_hash(const riop_desc &d, const void *uv, hipStream_t s) {
+    const size_t bytes = (size_t)d.M * 2 * (d.prec == RIOP_F64 ? 8 : 4);
+    std::vector<unsigned char> h(bytes);
+    if (bytes) {
+        RIOP_HIP(hipMemcpyAsync(h.data(), uv, bytes, hipMemcpyDeviceToHost, s));
+        RIOP_HIP(hipStreamSynchronize(s));
+    }
+    uint64_t x = 1469598103934665603ull;
+    for (unsigned char c : h) x = (x ^ c) * 1099511628211ull;
+    return x;
+}
 
 static double time_pairs(riop_plan *p, int reps, hipStream_t s) {
     DevBuf x, y;
@@ -80,7 +96,7 @@ static double time_pairs(riop_plan *p, int reps, hipStream_t s) {
 static riop_plan *tuned_plan(const riop_desc &d0, const void *uv, int reps, hipStream_t s, int *best_tile,
                              std::vector<double> &ms) {
     ms.assign(4, -1.0);
-    const auto key = std::make_tuple(d0.n, d0.M, d0.J, d0.prec);
+    const auto key = std::make_tuple(d0.n, d0.M, d0.J, (int)d0.prec, coverage_hash(d0, uv, s));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);

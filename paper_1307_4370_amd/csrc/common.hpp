@@ -208,8 +208,6 @@ struct riop_plan {
     int kdeg = 0;                // degree of the per-tap polynomial in s
     int n_even = 0, n_odd = 0;   // coefficients in the even / odd parts
     double kfit_err = 0;
-    riop::DevBuf kcoef;          // R[J/2][2][kMaxPoly]
-    std::vector<double> kcoef_host;  // same table on the host, double
     riop::DevBuf kcoef_compact;  // R[J/2][2][D/2 + 1] compact copy
     riop::DevBuf deapod;         // R[n]: d(p - n/2)
 

@@ -241,36 +241,9 @@ __global__ void tile_start_from_keys(const int *__restrict__ start, int ntiles, 
 // ---------------------------------------------------------------------------
 // Kernel weights.
 
-// Per-tap-pair polynomial coefficients, passed by value in the kernel
-// arguments so they live in scalar registers / the constant cache.
-template <typename R> struct KCoef {
-    R c[8][2][KDeg<R>::D / 2 + 1];  // [tap pair][even, odd][power of s^2]
-};
-
-template <typename R, int J>
-__device__ inline void kb_weights(R rho, const KCoef<R> &kc, R (&w)[J]) {
-    constexpr int D = KDeg<R>::D;
-    constexpr int NEV = D / 2 + 1;   // even coefficients s^0, s^2, ..., s^(2*(NEV-1))
-    constexpr int NOD = (D + 1) / 2; // odd coefficients s^1, s^3, ...
-    const R s = R(2) * rho - R(1);
-    const R u = s * s;
-#pragma unroll
-    for (int jp = 0; jp < J / 2; ++jp) {
-        const R *ce = kc.c[jp][0];
-        const R *co = kc.c[jp][1];
-        R e = ce[NEV - 1];
-#pragma unroll
-        for (int k = NEV - 2; k >= 0; --k) e = e * u + ce[k];
-        R o = co[NOD - 1];
-#pragma unroll
-        for (int k = NOD - 2; k >= 0; --k) o = o * u + co[k];
-        w[jp] = e + s * o;
-        w[J - 1 - jp] = e - s * o;
-    }
-}
-
-// Same weights with the coefficient table read through a pointer (global,
-// wave-uniform: scalar loads), laid out [pair][even/odd][KS].
+// Weights of the J taps at fractional offset rho, with the coefficient table
+// read through a pointer (global, wave-uniform: scalar loads), laid out
+// [pair][even/odd][KS].
 template <typename R, int J>
 __device__ inline void kb_weights_ptr(R rho, const R *__restrict__ kc, R (&w)[J]) {
     constexpr int D = KDeg<R>::D;
@@ -301,7 +274,7 @@ template <typename R> struct GridArgs {
     const uint32_t *cell;
     const R *frac;
     const int *perm;
-    KCoef<R> kc;
+    const R *kc;       // kernel coefficients [pair][even/odd][D/2 + 1]
     C<R> *vout;        // degrid output
     const C<R> *vin;   // grid input
     int K, T, tps;
@@ -318,8 +291,8 @@ __device__ inline void degrid_one(const GridArgs<R> &a, const C<R> *reg, int W, 
     const R fu = a.frac[2 * (int64_t)v], fv = a.frac[2 * (int64_t)v + 1];
     const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;
     R wu_[J], wv_[J];
-    kb_weights<R, J>(fu, a.kc, wu_);
-    kb_weights<R, J>(fv, a.kc, wv_);
+    kb_weights_ptr<R, J>(fu, a.kc, wu_);
+    kb_weights_ptr<R, J>(fv, a.kc, wv_);
     R ar = 0, ai = 0;
     const C<R> *base = reg + la * W + lb;
 #pragma unroll
@@ -962,11 +935,7 @@ template <typename R> static GridArgs<R> grid_args(riop_plan *p) {
     a.cell = p->cell.as<uint32_t>();
     a.frac = p->frac.as<R>();
     a.perm = p->perm.as<int>();
-    const std::vector<double> &hc = p->kcoef_host;
-    for (int jp = 0; jp < p->J / 2; ++jp)
-        for (int e = 0; e < 2; ++e)
-            for (int k = 0; k < KDeg<R>::D / 2 + 1; ++k)
-                a.kc.c[jp][e][k] = (R)hc[(size_t)(jp * 2 + e) * kMaxPoly + k];
+    a.kc = p->kcoef_compact.as<R>();
     a.K = p->K;
     a.T = p->tile;
     a.tps = p->tiles_per_side;

@@ -416,10 +416,16 @@ __device__ inline void store_region(const TileArgs<R> &a, const double *tre, con
                                     int nthreads) {
     const int T = a.T, K = a.K, RS = region_stride(T, J), lt = __builtin_ctz(T);
     const int ta = (t / a.tps) * T, tb = (t % a.tps) * T;
-    C<R> *gbase = a.grid + (int64_t)ta * K + tb;
-    for (int c = tid; c < T * T; c += nthreads) {
-        const int r = c >> lt, col = c & (T - 1);
-        gbase[(int64_t)r * K + col] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    C<R> *gbase = a.grid + (int64_t)ta * K + tb;  // T rows of K cells: 32-bit offsets below
+    // Two horizontally adjacent cells per step (T and RS are even): 16-byte
+    // LDS reads of each plane.
+    for (int c2 = tid; c2 < T * T / 2; c2 += nthreads) {
+        const int c = 2 * c2, r = c >> lt, col = c & (T - 1);
+        const double2 re = *reinterpret_cast<const double2 *>(tre + r * RS + col);
+        const double2 im = *reinterpret_cast<const double2 *>(tim + r * RS + col);
+        C<R> *g = gbase + r * K + col;
+        g[0] = mk<R>((R)re.x, (R)im.x);
+        g[1] = mk<R>((R)re.y, (R)im.y);
     }
     C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
     for (int c = tid; c < T * (J - 1); c += nthreads) {  // right strip
@@ -532,7 +538,10 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     const double p2sc = P2 ? *a.p2scale : 1.0;
     // The first slice's loads are in flight while the region is cleared.
     load(f_begin + lane);
-    for (int c = tid; c < 2 * PS; c += kThreads) tre[c] = 0.0;
+    {  // 16-byte stores (the region starts the LDS block; PS is even)
+        double2 *t2 = reinterpret_cast<double2 *>(tre);
+        for (int c = tid; c < PS; c += kThreads) t2[c] = make_double2(0.0, 0.0);
+    }
     __syncthreads();
 
     C<R> *wuv = wuv_all + wave * JR * SR;

@@ -286,13 +286,14 @@ constexpr int kDegridThreads = 256;
 constexpr int kPerThread = kUnit / kDegridThreads;
 
 template <typename R, int J, bool USER>
-__device__ inline void degrid_one(const GridArgs<R> &a, const C<R> *reg, int W, int ta, int tb, int v) {
+__device__ inline void degrid_one(const GridArgs<R> &a, const R *kc, const C<R> *reg, int W, int ta, int tb,
+                                  int v) {
     const uint32_t cv = a.cell[v];
     const R fu = a.frac[2 * (int64_t)v], fv = a.frac[2 * (int64_t)v + 1];
     const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;
     R wu_[J], wv_[J];
-    kb_weights_ptr<R, J>(fu, a.kc, wu_);
-    kb_weights_ptr<R, J>(fv, a.kc, wv_);
+    kb_weights_ptr<R, J>(fu, kc, wu_);
+    kb_weights_ptr<R, J>(fv, kc, wv_);
     R ar = 0, ai = 0;
     const C<R> *base = reg + la * W + lb;
 #pragma unroll
@@ -324,22 +325,35 @@ __global__ void __launch_bounds__(kDegridThreads) degrid_kernel(GridArgs<R> a) {
     const int W = a.T + J - 1;
     const int ta = (wu.tile / a.tps) * a.T, tb = (wu.tile % a.tps) * a.T;
     const int K = a.K;
-    // Region rows by wavefront, columns by lane (no divisions).
-    for (int i = threadIdx.x >> 6; i < W; i += kDegridThreads >> 6) {
+    // Region rows by wavefront (a wave-uniform row and row address), columns
+    // by lane (no divisions).
+    for (int i = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); i < W; i += kDegridThreads >> 6) {
         int gi = ta + i;
         if (gi >= K) gi -= K;
+        const C<R> *grow = a.grid + (int64_t)gi * K;
+        C<R> *lrow = reg + i * W;
         for (int j = threadIdx.x & 63; j < W; j += 64) {
             int gj = tb + j;
             if (gj >= K) gj -= K;
-            reg[i * W + j] = a.grid[(int64_t)gi * K + gj];
+            lrow[j] = grow[gj];
         }
+    }
+    // Single precision: the coefficient table (32 values at J = 8) in
+    // registers for the whole block, so no visibility reloads it.
+    constexpr int KS = KDeg<R>::D / 2 + 1, NKC = (J / 2) * 2 * KS;
+    const R *kc = a.kc;
+    R kcr[sizeof(R) == 4 ? NKC : 1];
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int i = 0; i < NKC; ++i) kcr[i] = a.kc[i];
+        kc = kcr;
     }
     __syncthreads();
     const int end = wu.start + wu.count;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         const int v = wu.start + threadIdx.x + k * kDegridThreads;
-        if (v < end) degrid_one<R, J, USER>(a, reg, W, ta, tb, v);
+        if (v < end) degrid_one<R, J, USER>(a, kc, reg, W, ta, tb, v);
     }
 }
 

@@ -360,9 +360,19 @@ __global__ void __launch_bounds__(kDegridThreads) degrid_kernel(GridArgs<R> a) {
 // ---------------------------------------------------------------------------
 // Gridding: one workgroup per sort tile.
 
-// Single-precision windows up to 8 wide are accumulated with matrix
-// instructions (v_mfma_f32_16x16x4_f32), the others with vector FMAs.
-template <typename R> __host__ __device__ constexpr bool grid_mfma(int J) { return sizeof(R) == 4 && J <= 8; }
+// Windows up to 8 wide are accumulated with matrix instructions
+// (v_mfma_f32_16x16x4_f32, v_mfma_f64_16x16x4_f64: the same operand layouts;
+// the accumulator rows differ, see the run close), wider ones with vector FMAs.
+template <typename R> __host__ __device__ constexpr bool grid_mfma(int J) { return J <= 8; }
+
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+__device__ inline mfma_f4 mfma_16x16x4(float a, float b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline mfma_d4 mfma_16x16x4(double a, double b, mfma_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // Row length of a wavefront's tap-major staging arrays.  Vector path: odd,
 // so the eight-address broadcast reads fall in distinct banks.  Matrix path:
@@ -593,24 +603,38 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     };
     // Matrix path state: lane l holds D[4 (l / 16) + r][l % 16], i.e. window
     // rows 2 (l / 16) and 2 (l / 16) + 1 (real, imaginary) of column slot l % 16.
-    typedef float mf4 __attribute__((ext_vector_type(4)));
-    mf4 dacc = {0.f, 0.f, 0.f, 0.f};
+    typedef R mf4 __attribute__((ext_vector_type(4)));
+    mf4 dacc = {R(0), R(0), R(0), R(0)};
     const int mk_ = lane >> 4, mi = lane & 15;
-    const int abase = 2 * ((mi >> 1) * SR + mk_) + (mi & 1);  // float index into wuv
+    const int abase = 2 * ((mi >> 1) * SR + mk_) + (mi & 1);  // real-part index into wuv
     const int bbase = mi * SR + mk_;                          // index into wv
     const int coff = 2 * mk_ * RS + mi;                       // this lane's first cell of a run block
     auto close_run_mf = [&](int pos) {
-        const int c = (pos >> 8) * RS + ((pos & 255) << 3) + coff;
+        if constexpr (sizeof(R) == 4) {
+            // f32 product: lane (mk_, mi) holds rows 4 mk_ .. 4 mk_ + 3, i.e.
+            // window rows 2 mk_ + h (h = 0, 1), real and imaginary.
+            const int c = (pos >> 8) * RS + ((pos & 255) << 3) + coff;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (2 * mk_ + h < J) {
-                __hip_atomic_fetch_add(tre + c + h * RS, (double)dacc[2 * h], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(tim + c + h * RS, (double)dacc[2 * h + 1], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int h = 0; h < 2; ++h) {
+                if (2 * mk_ + h < J) {
+                    __hip_atomic_fetch_add(tre + c + h * RS, (double)dacc[2 * h], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(tim + c + h * RS, (double)dacc[2 * h + 1], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
+        } else {
+            // f64 product: lane (mk_, mi) holds rows 4 r + mk_ (r = 0..3), i.e.
+            // window rows 2 r + (mk_ >> 1) of one part (mk_ & 1: imaginary).
+            double *plane = (mk_ & 1) ? tim : tre;
+            const int c = ((pos >> 8) + (mk_ >> 1)) * RS + ((pos & 255) << 3) + mi;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (2 * r + (mk_ >> 1) < J)
+                    __hip_atomic_fetch_add(plane + c + 2 * r * RS, (double)dacc[r], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        dacc = mf4{0.f, 0.f, 0.f, 0.f};
+        dacc = mf4{R(0), R(0), R(0), R(0)};
     };
     int cur = -1;  // packed window row and column block of the open run (-1: none yet)
 
@@ -663,15 +687,15 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
         if constexpr (MF) {
             // Groups of 4 entries; a group holding run starts is split into
             // products over the entries of each run (B masked by entry).
-            const float *wuf = reinterpret_cast<const float *>(wuv);
+            const R *wuf = reinterpret_cast<const R *>(wuv);
             if (nlive == 64) {
 #pragma unroll
                 for (int g = 0; g < 16; ++g) {
-                    const float av = wuf[abase + 8 * g];
-                    const float bv = wv[bbase + 4 * g];
+                    const R av = wuf[abase + 8 * g];
+                    const R bv = wv[bbase + 4 * g];
                     const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;
                     if (__builtin_expect(s4 == 0, 1)) {
-                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc, 0, 0, 0);
+                        dacc = mfma_16x16x4(av, bv, dacc);
                     } else {
                         unsigned m = s4;
                         int lo = 0;
@@ -679,26 +703,26 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
                             const int b = __builtin_ctz(m);
                             m &= m - 1;
                             if (b > lo) {
-                                const float bm = (mk_ >= lo && mk_ < b) ? bv : 0.f;
-                                dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                                const R bm = (mk_ >= lo && mk_ < b) ? bv : R(0);
+                                dacc = mfma_16x16x4(av, bm, dacc);
                             }
                             if (cur >= 0) close_run_mf(cur);
                             cur = __builtin_amdgcn_readlane(pos, 4 * g + b);
                             lo = b;
                         }
-                        const float bm = mk_ >= lo ? bv : 0.f;
-                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                        const R bm = mk_ >= lo ? bv : R(0);
+                        dacc = mfma_16x16x4(av, bm, dacc);
                     }
                 }
             } else {  // a partial slice: its groups past the last live entry are all zero
                 const int ng = (nlive + 3) >> 2;
 #pragma unroll 1
                 for (int g = 0; g < ng; ++g) {
-                    const float av = wuf[abase + 8 * g];
-                    const float bv = wv[bbase + 4 * g];
+                    const R av = wuf[abase + 8 * g];
+                    const R bv = wv[bbase + 4 * g];
                     const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;
                     if (__builtin_expect(s4 == 0, 1)) {
-                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, dacc, 0, 0, 0);
+                        dacc = mfma_16x16x4(av, bv, dacc);
                     } else {
                         unsigned m = s4;
                         int lo = 0;
@@ -706,15 +730,15 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
                             const int b = __builtin_ctz(m);
                             m &= m - 1;
                             if (b > lo) {
-                                const float bm = (mk_ >= lo && mk_ < b) ? bv : 0.f;
-                                dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                                const R bm = (mk_ >= lo && mk_ < b) ? bv : R(0);
+                                dacc = mfma_16x16x4(av, bm, dacc);
                             }
                             if (cur >= 0) close_run_mf(cur);
                             cur = __builtin_amdgcn_readlane(pos, 4 * g + b);
                             lo = b;
                         }
-                        const float bm = mk_ >= lo ? bv : 0.f;
-                        dacc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm, dacc, 0, 0, 0);
+                        const R bm = mk_ >= lo ? bv : R(0);
+                        dacc = mfma_16x16x4(av, bm, dacc);
                     }
                 }
             }

@@ -379,7 +379,15 @@ __device__ inline mfma_d4 mfma_16x16x4(double a, double b, mfma_d4 c) {
 // 4 mod 32, so the operand reads (16 rows x 4 entries per instruction) hit 64
 // distinct banks.  Either way the staging stores (consecutive lanes) are
 // conflict-free.
-template <typename R> __host__ __device__ constexpr int slice_row(int J) { return grid_mfma<R>(J) ? 68 : 65; }
+// Entries per staged slice: 32 on the double-precision matrix path (one lane
+// per entry and axis, which halves the staging area so that two workgroups
+// fit per CU), 64 otherwise (one lane per entry).
+template <typename R> __host__ __device__ constexpr int slice_len(int J) {
+    return grid_mfma<R>(J) && sizeof(R) == 8 ? 32 : 64;
+}
+template <typename R> __host__ __device__ constexpr int slice_row(int J) {
+    return grid_mfma<R>(J) ? (slice_len<R>(J) == 32 ? 36 : 68) : 65;
+}
 
 // LDS bytes of one wavefront's staging area.
 template <typename R> __host__ __device__ constexpr int grid_stage_bytes(int J) {
@@ -502,6 +510,7 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     constexpr bool MF = grid_mfma<R>(J);
     constexpr int JR = MF ? 8 : J;   // staged row-weight rows
     constexpr int SR = slice_row<R>(J);
+    constexpr int SL = slice_len<R>(J);
     constexpr int BATCH = sizeof(R) == 8 ? (J > 12 ? 2 : 4) : (J > 8 ? 4 : 8);
     // Kernel coefficients through scalar loads where they fit in scalar
     // registers alongside everything else, else from an LDS copy.
@@ -535,6 +544,11 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     const int ta = (t / tps) * T, tb = (t % tps) * T;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, li = lane >> 3, lj = lane & 7;
+    // 32-entry slices: lane = entry + 32 axis stages one axis of one entry
+    // (axis 0: u, with the value; axis 1: v).  64-entry slices: lane = entry,
+    // both axes.
+    constexpr bool SPLIT = SL == 32;
+    const int e = SPLIT ? (lane & 31) : lane, ax = SPLIT ? (lane >> 5) : 0;
     // This wavefront's share of the tile's visibilities (tile-relative).
     const int f_begin = (int)(((int64_t)wave * total) / kWaves);
     const int f_end = (int)(((int64_t)(wave + 1) * total) / kWaves);
@@ -548,20 +562,26 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
         if (f < f_end) {
             const int v = v0 + f;
             cv = a.cell[v];
-            fu = a.frac[2 * (int64_t)v];
-            fv = a.frac[2 * (int64_t)v + 1];
-            if constexpr (P2) {
-                ps = a.p2s[v];
-                pz = a.p2z[v];
-                py = a.p2y[v];
+            if constexpr (SPLIT) {
+                fu = a.frac[2 * (int64_t)v + ax];  // this lane's axis
             } else {
-                val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
+                fu = a.frac[2 * (int64_t)v];
+                fv = a.frac[2 * (int64_t)v + 1];
+            }
+            if (ax == 0) {
+                if constexpr (P2) {
+                    ps = a.p2s[v];
+                    pz = a.p2z[v];
+                    py = a.p2y[v];
+                } else {
+                    val = a.vin[USER ? (int64_t)a.perm[v] : (int64_t)v];
+                }
             }
         }
     };
     const double p2sc = P2 ? *a.p2scale : 1.0;
     // The first slice's loads are in flight while the region is cleared.
-    load(f_begin + lane);
+    load(f_begin + e);
     {  // 16-byte stores (the region starts the LDS block; PS is even)
         double2 *t2 = reinterpret_cast<double2 *>(tre);
         for (int c = tid; c < PS; c += kThreads) t2[c] = make_double2(0.0, 0.0);
@@ -638,15 +658,15 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
     };
     int cur = -1;  // packed window row and column block of the open run (-1: none yet)
 
-    for (int base = f_begin; base < f_end; base += 64) {
-        const int nlive = min(64, f_end - base);
-        const bool live = lane < nlive;
+    for (int base = f_begin; base < f_end; base += SL) {
+        const int nlive = min(SL, f_end - base);
+        const bool live = e < nlive;
         if constexpr (P2) {
-            if (live) {
+            if (live && ax == 0) {
                 const double vr = (double)ps.x + pz.x, vi = (double)ps.y + pz.y;
                 const double rr = py.x + (vr - py.x) * p2sc, ri = py.y + (vi - py.y) * p2sc;
                 const double znr = vr - rr, zni = vi - ri;
-                a.p2z[v0 + base + lane] = mk<R>((R)znr, (R)zni);
+                a.p2z[v0 + base + e] = mk<R>((R)znr, (R)zni);
                 val = mk<R>((R)(rr - znr - ps.x), (R)(ri - zni - ps.y));
             }
         }
@@ -654,9 +674,26 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
         // accumulation below runs over all 64 entries without bound tests.
         if (!live) val = mk<R>(0, 0);
         const int la = (int)(cv & 0xffffu) - ta, lb = (int)(cv >> 16) - tb;  // in [0, T)
-        const int pos = live ? (la << 8) | (lb >> 3) : -1;
+        const int pos = (live && ax == 0) ? (la << 8) | (lb >> 3) : -1;
         const int db = lb & 7;
-        {
+        if constexpr (SPLIT) {
+            R w_[J];
+            if constexpr (kScalarCoef) kb_weights_ptr<R, J>(fu, a.kc, w_);
+            else kb_weights_ptr<R, J>(fu, kcl, w_);
+            if (ax == 0) {
+#pragma unroll
+                for (int i = 0; i < J; ++i) wuv[i * SR + e] = mk<R>(w_[i] * val.x, w_[i] * val.y);
+            } else {
+                // Column weights at rows db .. db + J - 1, zeros in the other
+                // rows: all rows cleared at fixed offsets, then the weights
+                // written over them (one wavefront's LDS writes land in order).
+#pragma unroll
+                for (int r = 0; r < NC; ++r) wv[r * SR + e] = R(0);
+                R *wcol = wv + db * SR + e;
+#pragma unroll
+                for (int j = 0; j < J; ++j) wcol[j * SR] = w_[j];
+            }
+        } else {
             R wu_[J], wv_[J];
             if constexpr (kScalarCoef) {
                 kb_weights_ptr<R, J>(fu, a.kc, wu_);
@@ -679,18 +716,18 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
         // Run starts: entries whose window row or column block differs from
         // the previous entry's (lane 0 compares with the open run).
         const int prev = __builtin_amdgcn_update_dpp(cur, pos, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
-        const uint64_t starts = __ballot(live && pos != prev);
+        const uint64_t starts = __ballot(live && ax == 0 && pos != prev);
         __builtin_amdgcn_wave_barrier();
         // The next slice's visibility: global loads in flight during the accumulation.
-        load(base + 64 + lane);
+        load(base + SL + e);
 
         if constexpr (MF) {
             // Groups of 4 entries; a group holding run starts is split into
             // products over the entries of each run (B masked by entry).
             const R *wuf = reinterpret_cast<const R *>(wuv);
-            if (nlive == 64) {
+            if (nlive == SL) {
 #pragma unroll
-                for (int g = 0; g < 16; ++g) {
+                for (int g = 0; g < SL / 4; ++g) {
                     const R av = wuf[abase + 8 * g];
                     const R bv = wv[bbase + 4 * g];
                     const unsigned s4 = (unsigned)(starts >> (4 * g)) & 0xFu;

@@ -94,7 +94,7 @@ def test_blocked_limit_is_optimal():
     assert all(fid(v, idx, e) >= -1e-8 * e ** 2 for idx, e in zip(parts, eps))
     fr = float(np.abs(Pd @ v[:N]).sum())
     gam = 0.05 * np.abs(sara.psi_adj(op.phi_adj(y))).max()
-    xh, _, hist, _ = blocks.sdmm_blocks(y, eps, parts, op, sara, T=1500, n_cg=40, gamma=gam)
+    xh, _, hist, _ = blocks.sdmm_blocks(y, eps, parts, op, sara, T=600, n_cg=20, gamma=gam)
     xr = np.real(xh)
     for idx, e in zip(parts, eps):
         assert np.linalg.norm(y[idx] - op.phi(xr)[idx]) <= e * (1 + 1e-3)

@@ -92,7 +92,7 @@ def test_log_sum_penalty_decreases_across_passes():
     prev = None
     for k in range(4):
         w = None if x is None else reweight.weights(sara.psi_adj(np.real(x)), delta)
-        x, _, _, _ = sdmm.sdmm(y, eps, op, sara, T=1500, n_cg=40, gamma=gam, weights=w, x0=x)
+        x, _, _, _ = sdmm.sdmm(y, eps, op, sara, T=600, n_cg=20, gamma=gam, weights=w, x0=x)
         pen = float(np.sum(np.log(delta + np.abs(sara.psi_adj(np.real(x))))))
         if prev is not None:
             assert pen <= prev + 1e-6 * abs(prev), (k, pen, prev)

@@ -183,7 +183,7 @@ def test_sdmm_limit_is_optimal(weighted):
         weights = W.rng(103, 12).uniform(0.5, 2.0, size=(sara.q, op.n, op.n))
     xr, fr = _reference_solution(op, sara, y, eps, weights)
     gam = 0.05 * np.abs(sara.psi_adj(op.phi_adj(y))).max()
-    xh, _, hist, _ = sdmm.sdmm(y, eps, op, sara, T=1500, n_cg=40, gamma=gam, weights=weights)
+    xh, _, hist, _ = sdmm.sdmm(y, eps, op, sara, T=900, n_cg=24, gamma=gam, weights=weights)
     f_sdmm = sdmm.f1_value(sara.psi_adj(np.real(xh)), weights)
     # Feasible (to SDMM's convergence) and the same optimal value.
     assert np.linalg.norm(y - op.phi(np.real(xh))) <= eps * (1 + 1e-3)

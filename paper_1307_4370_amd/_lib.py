@@ -332,6 +332,22 @@ class Plan:
         return x, stats, history, state
 
 
+    def sdmm_enqueue(self, y, eps: float, T: int, n_cg: int = 16, gamma: float = 0.0, beta: float = 1e-3,
+                     cg_tol: float = 0.0, stream=None):
+        """Algorithm 1's set-up and T iterations enqueued without waiting
+        (riop_sdmm_init, riop_sdmm_step); sdmm_collect returns the result."""
+        y = self._c(y, (self.M,), "y")
+        prm = SdmmParams(T=T, n_cg=n_cg, gamma=gamma, beta=beta, xi=1e-3, tau=0.1, cg_tol=float(cg_tol))
+        _check(lib().riop_sdmm_init(self._h, y.data_ptr(), float(eps), ctypes.byref(prm), None, _stream(stream)))
+        _check(lib().riop_sdmm_step(self._h, int(T), _stream(stream)))
+
+    def sdmm_collect(self, stream=None):
+        """(x, stats) of the run enqueued by sdmm_enqueue (riop_sdmm_finish; synchronises)."""
+        x = self._new((self.n, self.n))
+        st = SdmmStats()
+        _check(lib().riop_sdmm_finish(self._h, None, x.data_ptr(), ctypes.byref(st), _stream(stream)))
+        return x, {k: getattr(st, k) for k, _ in SdmmStats._fields_}
+
     def sdmm_tv(self, y, eps: float, T: int, n_cg: int = 16, n_inner: int = 20, weights=None, gamma: float = 0.0,
                 beta: float = 1e-3, x0=None, reweight: dict | None = None, cg_tol: float = 0.0,
                 early_stop: bool = False, xi: float = 1e-3, tau: float = 0.1, stream=None):

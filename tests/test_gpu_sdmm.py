@@ -246,3 +246,20 @@ def test_sdmm_rejects_bad_arguments():
     for bad_eps in (0.0, -1.0, float("inf")):
         with pytest.raises(RiopError):
             plan.sdmm(to_dev(y, "f64"), bad_eps, T=1)
+
+
+def test_enqueued_run_equals_sdmm():
+    """riop_sdmm_init + riop_sdmm_step + riop_sdmm_finish (no host wait
+    between set-up and iterations) give the iterate of riop_sdmm."""
+    device()
+    announce("sdmm enqueued (init/step/finish) vs riop_sdmm, f64")
+    c = W.C1
+    _, uv, _, y, eps = _problem(c, "f64")
+    plan = _plan(c, uv, "f64")
+    yd = to_dev(y, "f64")
+    xa, sa, _, _ = plan.sdmm(yd, eps, T=6, n_cg=8)
+    plan.sdmm_enqueue(yd, eps, T=6, n_cg=8)
+    xb, sb = plan.sdmm_collect()
+    assert rel(host(xb), host(xa)) <= 1e-14
+    assert sb["iters"] == sa["iters"] == 6
+    assert sb["nu"] == pytest.approx(sa["nu"], rel=1e-14)

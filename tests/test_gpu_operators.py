@@ -69,6 +69,23 @@ def test_wide_kernels(prec, J):
     assert rel(host(plan.phi_adj(to_dev(w[perm], prec), sorted=True)), op.phi_adj(w)) <= TOL[prec]
 
 
+@pytest.mark.parametrize("J,tile", [(2, 8), (4, 8), (4, 32), (6, 64)])
+def test_narrow_kernels_double(J, tile):
+    """Kernel widths 2 and 4 on the double-precision matrix path (single
+    precision needs J >= 6), and J = 6 with the 64-wide tile (two wavefronts
+    per workgroup), both orders."""
+    n, M, prec = 64, 2500, "f64"
+    device()
+    announce(f"narrow kernel J={J} tile={tile} {prec}")
+    uv, x, w = _inputs(n, M, prec, 15)
+    op = nufft.Operator(n, uv, J)
+    plan = _plan(n, uv, J, prec, tile=tile)
+    assert rel(host(plan.phi(to_dev(x, prec))), op.phi(x)) <= TOL[prec]
+    assert rel(host(plan.phi_adj(to_dev(w, prec))), op.phi_adj(w)) <= TOL[prec]
+    perm = host(plan.layout()[0]).real.astype(np.int64)
+    assert rel(host(plan.phi_adj(to_dev(w[perm], prec), sorted=True)), op.phi_adj(w)) <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("tile", [8, 16, 32, 64])
 def test_tile_shapes_agree(prec, tile):

@@ -594,6 +594,22 @@ def main():
                                     if v[1] and algorithmic_bytes(k, n, M, cb) else None)}
             for k, v in kernels.items() if v[1]}
 
+    # A whole solve of this workload from x = 0: its T iterations (Algorithm 1
+    # with the same parameters), timed, and the reconstruction quality of the
+    # synthetic sky (SNR = 20 log10 ||x|| / ||x - Re x_hat||).
+    solve = None
+    if not args.no_extras:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        xs, sts, _, _ = plan.sdmm(y, eps, T=c.T, n_cg=ncg)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - a
+        xr = xs.real.double().cpu().numpy()
+        snr = 20 * math.log10(float(np.linalg.norm(x_true)) / float(np.linalg.norm(x_true - xr)))
+        solve = {"iterations": sts["iters"], "seconds": round(t_solve, 3), "nu": sts["nu"], "zeta": sts["zeta"],
+                 "snr_db": round(snr, 2), "note": "FP32, from x = 0, stream launches; set-up included"}
+        log(f"solve: {solve}")
+
     # Stand-alone Phi + Phi^dagger pairs (caller order and plan order).
     def pair_rate(p, xin, yin, sorted_, reps):
         for _ in range(2):
@@ -690,6 +706,7 @@ def main():
         "kernels": kern,
         "cpu_baseline": cpu,
         "s1_errors": s1 or None,
+        "solve": solve,
         "small_workloads": extras.get("small"),
         "gram_vs_degrid_grid": extras.get("gram"),
         "batch_s2": s2,

@@ -135,6 +135,25 @@ def test_fullsize_sdmm_against_oracle(point_data, prec, tol_x):
           f"{_sampled_rel(xg, sample, ref['x_sample']):.3e}, nu {hist[-1][2]:.6f}", flush=True)
 
 
+def test_fullsize_sdmm_graph_replay_against_oracle(point_data):
+    """The same FP32 run as one captured HIP graph replayed (a one-channel
+    batch, the form bench.py also times) against the stored oracle values."""
+    device()
+    announce("full-size SDMM T=2 n_cg=16 as a replayed graph vs oracle fixture, f32")
+    from paper_1307_4370_amd import Batch
+    uv, y, eps, sample, ref = point_data
+    T, n_cg = int(ref["T"]), int(ref["n_cg"])
+    bt = Batch([(C.n, to_dev(uv, "f32"))], J=C.J, levels=C.levels, prec="f32", autotune=False)
+    xs, stats = bt.sdmm([to_dev(y, "f32")], [eps], T=T, n_cg=n_cg, iters_per_graph=T)
+    xg = host(xs[0])
+    bt.close()
+    assert stats[0]["iters"] == T
+    assert stats[0]["gamma"] == pytest.approx(float(ref["gamma"]), rel=1e-5)
+    assert stats[0]["nu"] == pytest.approx(float(ref["nu"][T - 1]), rel=1e-4)
+    assert _sampled_rel(xg, sample, ref["x_sample"]) <= 1e-4
+    assert np.linalg.norm(xg) == pytest.approx(float(ref["x_norm"]), rel=1e-4)
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 5e-7), ("f32", 1e-6)])
 def test_fullsize_phi_of_point_sources_is_the_exact_sum(prec, tol):
     """Every one of the M outputs of Phi against the exact measurement of the

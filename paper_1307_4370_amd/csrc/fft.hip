@@ -349,14 +349,19 @@ fft_pass_p2(FftArgs<R> a) {
 #pragma unroll
                 for (int e = 0; e < E; ++e)
                     rv[e] = ((e < 2 || e >= 6) && active) ? a.cg_r[t + (long)band(e) * ies] : mk<R>(0, 0);
+                // Each wavefront sums the partials itself (no barrier): lane
+                // strides, then an XOR butterfly, whose partner lanes add the
+                // same two values, so every wavefront gets the identical sums.
+                const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
                 double so = 0.0, sn = 0.0;
-                for (int i = threadIdx.x; i < a.cg_nred; i += blockDim.x) {
+                for (int i = threadIdx.x & 63; i < a.cg_nred; i += width) {
                     so += a.cg_part[a.cg_old * a.cg_nred + i];
                     sn += a.cg_part[a.cg_new * a.cg_nred + i];
                 }
-                double *red = reinterpret_cast<double *>(smem);
-                so = block_sum_all(so, red);
-                sn = block_sum_all(sn, red);
+                for (int o = width >> 1; o > 0; o >>= 1) {
+                    so += __shfl_xor(so, o);
+                    sn += __shfl_xor(sn, o);
+                }
                 const double beta = so == 0.0 ? 0.0 : sn / so;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {

@@ -351,42 +351,65 @@ __device__ inline void syn_tile(const SynArgs<R> &a, int bi, const SynRegion<R> 
     }
     __syncthreads();
     // Columns (axis 0): lo1[ii][c] from (LL, HL), hi1[ii][c] from (LH, HH).
-    for (int idx = threadIdx.x; idx < TS * KR; idx += blockDim.x) {
-        const int ii = idx / KR, c = idx - ii * KR;
-        R lr = 0, li = 0, hr = 0, hi = 0;
-        const int par = ii & 1, base = ii / 2 + Lf / 2 - 1;
+    // Output rows 2 r and 2 r + 1 read the same Lf / 2 input rows (even and
+    // odd taps), so one thread forms both from one set of LDS reads.
+    for (int w = threadIdx.x; w < (TS / 2) * KR; w += blockDim.x) {
+        const int rp = w / KR, c = w - rp * KR;
+        R lr0 = 0, li0 = 0, hr0 = 0, hi0 = 0, lr1 = 0, li1 = 0, hr1 = 0, hi1_ = 0;
+        const int base = rp + Lf / 2 - 1;
         for (int t = 0; t < Lf / 2; ++t) {
-            const int m = par + 2 * t;
             const int r = base - t;
             const C<R> vll = LL[r * KR + c], vhl = HL[r * KR + c];
             const C<R> vlh = LH[r * KR + c], vhh = HH[r * KR + c];
-            lr += h[m] * vll.x + g[m] * vhl.x;
-            li += h[m] * vll.y + g[m] * vhl.y;
-            hr += h[m] * vlh.x + g[m] * vhh.x;
-            hi += h[m] * vlh.y + g[m] * vhh.y;
+            const int m0 = 2 * t, m1 = 2 * t + 1;
+            lr0 += h[m0] * vll.x + g[m0] * vhl.x;
+            li0 += h[m0] * vll.y + g[m0] * vhl.y;
+            hr0 += h[m0] * vlh.x + g[m0] * vhh.x;
+            hi0 += h[m0] * vlh.y + g[m0] * vhh.y;
+            lr1 += h[m1] * vll.x + g[m1] * vhl.x;
+            li1 += h[m1] * vll.y + g[m1] * vhl.y;
+            hr1 += h[m1] * vlh.x + g[m1] * vhh.x;
+            hi1_ += h[m1] * vlh.y + g[m1] * vhh.y;
         }
-        lo1[idx] = mk<R>(lr, li);
-        hi1[idx] = mk<R>(hr, hi);
+        lo1[(2 * rp) * KR + c] = mk<R>(lr0, li0);
+        hi1[(2 * rp) * KR + c] = mk<R>(hr0, hi0);
+        lo1[(2 * rp + 1) * KR + c] = mk<R>(lr1, li1);
+        hi1[(2 * rp + 1) * KR + c] = mk<R>(hr1, hi1_);
     }
     __syncthreads();
-    // Rows (axis 1).
+    // Rows (axis 1), output columns 2 c and 2 c + 1 of a row per thread and
+    // step from the same Lf / 2 inputs (see syn_out for the ownership).
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
-        if (idx >= TS * TS) break;
-        const int ii = idx / TS, jj = idx - ii * TS;
-        const int par = jj & 1, base = jj / 2 + Lf / 2 - 1;
-        R xr = 0, xi = 0;
+    for (int k = 0; k < 2; ++k) {
+        const int w = threadIdx.x + k * blockDim.x;
+        if (w >= TS * TS / 2) break;
+        const int ii = w / (TS / 2), cp = w - ii * (TS / 2);
+        const int base = cp + Lf / 2 - 1;
+        R xr0 = 0, xi0 = 0, xr1 = 0, xi1 = 0;
         for (int t = 0; t < Lf / 2; ++t) {
-            const int m = par + 2 * t;
             const int c = base - t;
             const C<R> vl = lo1[ii * KR + c], vh = hi1[ii * KR + c];
-            xr += h[m] * vl.x + g[m] * vh.x;
-            xi += h[m] * vl.y + g[m] * vh.y;
+            const int m0 = 2 * t, m1 = 2 * t + 1;
+            xr0 += h[m0] * vl.x + g[m0] * vh.x;
+            xi0 += h[m0] * vl.y + g[m0] * vh.y;
+            xr1 += h[m1] * vl.x + g[m1] * vh.x;
+            xi1 += h[m1] * vl.y + g[m1] * vh.y;
         }
-        acc[q].x += xr;
-        acc[q].y += xi;
+        acc[2 * k].x += xr0;
+        acc[2 * k].y += xi0;
+        acc[2 * k + 1].x += xr1;
+        acc[2 * k + 1].y += xi1;
     }
+}
+
+// Output owned by accumulator q of this thread in a (2 TO)^2 synthesis tile:
+// step q / 2 of the row pass, column parity q % 2 (false past the tile).
+__device__ inline bool syn_out(int q, int TS, int &ii, int &jj) {
+    const int w = threadIdx.x + (q >> 1) * blockDim.x;
+    if (w >= TS * TS / 2) return false;
+    ii = w / (TS / 2);
+    jj = 2 * (w - ii * (TS / 2)) + (q & 1);
+    return true;
 }
 
 // Levels > 1: one basis per blockIdx.y, writes the finer LL slot.
@@ -407,10 +430,8 @@ template <typename R> __global__ void __launch_bounds__(256) dwt_synthesis(SynAr
     }
     C<R> *out = a.ll_out + bi * a.ll_out_bstride;
     for (int q = 0; q < 4; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
-        if (idx >= TS * TS) break;
-        const int ii = idx / TS, jj = idx - ii * TS;
-        out[(long)(i0 + ii) * a.s + j0 + jj] = acc[q];
+        int ii, jj;
+        if (syn_out(q, TS, ii, jj)) out[(long)(i0 + ii) * a.s + j0 + jj] = acc[q];
     }
 }
 
@@ -437,9 +458,8 @@ template <typename R> __global__ void __launch_bounds__(256) dwt_synthesis_final
     }
     const int n = a.n;
     for (int q = 0; q < 4; ++q) {
-        const int idx = threadIdx.x + q * blockDim.x;
-        if (idx >= TS * TS) break;
-        const int ii = idx / TS, jj = idx - ii * TS;
+        int ii, jj;
+        if (!syn_out(q, TS, ii, jj)) continue;
         const long o = (long)(i0 + ii) * n + j0 + jj;
         C<R> v = acc[q];
         if (a.dirac_plane >= 0) v = cadd<R>(v, a.alpha[(long)a.dirac_plane * n * n + o]);

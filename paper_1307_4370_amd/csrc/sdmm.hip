@@ -67,30 +67,6 @@ __device__ inline double block_max(double v) {
     return r;
 }
 
-// Sum of one slot's partials, formed by each wavefront on its own (no
-// barrier): lane l adds entries l, l + 64, ..., then an XOR butterfly over the
-// lanes.  Each butterfly step adds the same two values on both partner lanes,
-// so every lane, wavefront and block obtains the identical sum.
-__device__ inline double slot_sum_wave(const double *partials, int slot) {
-    const int lane = threadIdx.x & 63;
-    double v = 0;
-    for (int i = lane; i < kRedBlocks; i += 64) v += partials[slot * kRedBlocks + i];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// Block sum for blocks of kRedThreads: butterflies within each wavefront,
-// then the wavefront sums in order (the result is meant for thread 0).
-__device__ inline double block_sum_waves(double v) {
-    __shared__ double red[kRedThreads / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0;
-    for (int w = 0; w < kRedThreads / 64; ++w) s += red[w];
-    return s;
-}
-
 // Sum of one slot's partials, in a fixed order, computed by the whole block.
 __device__ inline double slot_sum(const double *partials, int slot) {
     __shared__ double tot;
@@ -169,30 +145,11 @@ template <typename R> __global__ void cg_pq(const C<R> *p, C<R> *qp, long N, dou
 // alpha = rr_old / pq ; x += alpha p ; r -= alpha qp ; slot_new <- sum |r|^2.
 // With tol2 > 0, CG stops (alpha = 0 from then on, the iterate frozen) once
 // |r|^2 <= tol2 |r_0|^2, r_0 the initial residual (first = 1 records |r_0|^2).
-// The first chunk's loads are issued before the partial sums are read, so the
-// two latencies overlap; alpha is reduced per wavefront, with no barrier.
-constexpr int kUcg = 8;
 template <typename R>
-__global__ void __launch_bounds__(kRedThreads) cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long N,
-                                                        double *partials, int slot_old, int slot_pq, int slot_new,
-                                                        double *scalars, double tol2, int first) {
-    const long st = (long)gridDim.x * blockDim.x;
-    long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    C<R> pv[kUcg], qv[kUcg], xv[kUcg], rv[kUcg];
-    auto load = [&](long b) {
-#pragma unroll
-        for (int u = 0; u < kUcg; ++u)
-            if (b + u * st < N) {
-                const long i = b + u * st;
-                pv[u] = p[i];
-                qv[u] = qp[i];
-                xv[u] = x[i];
-                rv[u] = r[i];
-            }
-    };
-    load(i0);
-    const double rr = slot_sum_wave(partials, slot_old);
-    const double pq = slot_sum_wave(partials, slot_pq);
+__global__ void cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long N, double *partials, int slot_old,
+                          int slot_pq, int slot_new, double *scalars, double tol2, int first) {
+    const double rr = slot_sum(partials, slot_old);
+    const double pq = slot_sum(partials, slot_pq);
     const double rr0 = first ? rr : scalars[SC_RR0];
     const bool converged = tol2 > 0.0 && rr <= tol2 * rr0;
     const double alpha = (rr == 0.0 || pq == 0.0 || converged) ? 0.0 : rr / pq;
@@ -201,23 +158,29 @@ __global__ void __launch_bounds__(kRedThreads) cg_update(C<R> *x, C<R> *r, const
         if (alpha != 0.0) scalars[SC_CGIT] += 1.0;
     }
     double acc = 0;
-    for (bool head = true; i0 < N; i0 += kUcg * st, head = false) {
-        if (!head) load(i0);
-#pragma unroll
-        for (int u = 0; u < kUcg; ++u)
-            if (i0 + u * st < N) {
-                const long i = i0 + u * st;
-                C<R> xi = xv[u], ri = rv[u];
-                xi.x = (R)((double)xi.x + alpha * pv[u].x);
-                xi.y = (R)((double)xi.y + alpha * pv[u].y);
-                ri.x = (R)((double)ri.x - alpha * qv[u].x);
-                ri.y = (R)((double)ri.y - alpha * qv[u].y);
-                x[i] = xi;
-                r[i] = ri;
-                acc += abs2<R>(ri);
-            }
+    CHUNK_LOOP(i0, st, N) {
+        C<R> pv[kU], qv[kU], xv[kU], rv[kU];
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            pv[u] = p[i];
+            qv[u] = qp[i];
+            xv[u] = x[i];
+            rv[u] = r[i];
+        }
+        FOR_U(u) if (i0 + u * st < N) {
+            const long i = i0 + u * st;
+            C<R> xi = xv[u], ri = rv[u];
+            xi.x = (R)((double)xi.x + alpha * pv[u].x);
+            xi.y = (R)((double)xi.y + alpha * pv[u].y);
+            ri.x = (R)((double)ri.x - alpha * qv[u].x);
+            ri.y = (R)((double)ri.y - alpha * qv[u].y);
+            x[i] = xi;
+            r[i] = ri;
+            acc += abs2<R>(ri);
+        }
     }
-    const double s = block_sum_waves(acc);
+    __syncthreads();
+    const double s = block_sum(acc);
     if (threadIdx.x == 0) partials[slot_new * kRedBlocks + blockIdx.x] = s;
 }
 

@@ -391,18 +391,22 @@ fft_pass_p2(FftArgs<R> a) {
             if (a.halo) {
                 const int T = a.hT, J1 = a.hJ - 1, tps = a.htps, lt = __builtin_ctz(T);
                 const int lw = J1 <= 8 ? 3 : 4, NL = tps << lw;
-                const int HC = T * J1 + J1 * (T + J1);
+                // Halo layout (gridding): right strips by grid row, row k1's
+                // tps (J - 1) cells contiguous, then the bottom strips tile by
+                // tile, BC = (J - 1)(T + J - 1) cells each.
+                const int BC = J1 * (T + J1);
                 const int k1 = (int)t, dr = k1 >> lt, i = k1 & (T - 1);
                 const int upr = dr == 0 ? tps - 1 : dr - 1;
-                const C<R> *hrow = a.halo + (long)dr * tps * HC + i * J1;                   // left parts
-                const C<R> *hup = a.halo + (long)upr * tps * HC + T * J1 + i * (T + J1);  // above, above-left
+                const C<R> *hrow = a.halo + (long)k1 * tps * J1;                            // left parts
+                const C<R> *hup = a.halo + (long)tps * tps * T * J1 + (long)upr * tps * BC +
+                                  i * (T + J1);                                             // above, above-left
                 // The above tile's part (rows i < J - 1), loaded with the
                 // line so that the latencies overlap.
                 C<R> up[E];
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int k2 = jt + e * NE, dc = k2 >> lt, j = k2 & (T - 1);
-                    up[e] = (active && i < J1) ? hup[dc * HC + j] : mk<R>(0, 0);
+                    up[e] = (active && i < J1) ? hup[dc * BC + j] : mk<R>(0, 0);
                 }
                 C<R> hl[4], hu[4];
 #pragma unroll
@@ -410,8 +414,8 @@ fft_pass_p2(FftArgs<R> a) {
                     const int f = jt + q * NE, dc = f >> lw, j = f & ((1 << lw) - 1);
                     const int lc = dc == 0 ? tps - 1 : dc - 1;
                     const bool use = active && f < NL && j < J1;
-                    hl[q] = use ? hrow[lc * HC + j] : mk<R>(0, 0);
-                    hu[q] = (use && i < J1) ? hup[lc * HC + T + j] : mk<R>(0, 0);
+                    hl[q] = use ? hrow[lc * J1 + j] : mk<R>(0, 0);
+                    hu[q] = (use && i < J1) ? hup[lc * BC + T + j] : mk<R>(0, 0);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {

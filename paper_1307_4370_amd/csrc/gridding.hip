@@ -419,6 +419,17 @@ template <typename R> static size_t grid_lds(int T, int J, int waves) {
 // the right (right strip, T x (J-1)), below and below-right (bottom strip,
 // (J-1) x (T+J-1)).
 __host__ __device__ constexpr int halo_cells(int T, int J) { return T * (J - 1) + (J - 1) * (T + J - 1); }
+// Halo buffer layout.  Right strips first, by grid row: row i of tile (dr,
+// dc) at ((dr T + i) tps + dc) (J - 1), so that the left parts one grid row
+// receives are one contiguous run of tps (J - 1) cells.  Then the bottom
+// strips (with the corner), tile by tile: (J - 1) rows of T + J - 1 cells at
+// ntiles T (J - 1) + t (J - 1)(T + J - 1).
+__host__ __device__ inline int64_t halo_right(int T, int J, int tps, int dr, int i, int dc) {
+    return ((int64_t)(dr * T + i) * tps + dc) * (J - 1);
+}
+__host__ __device__ inline int64_t halo_bottom(int T, int J, int tps, int t) {
+    return (int64_t)tps * tps * T * (J - 1) + (int64_t)t * (J - 1) * (T + J - 1);
+}
 
 template <typename R> struct TileArgs {
     C<R> *grid;               // own T x T cells of every tile
@@ -459,17 +470,20 @@ __device__ inline void store_region(const TileArgs<R> &a, const double *tre, con
         g[0] = mk<R>((R)re.x, (R)im.x);
         g[1] = mk<R>((R)re.y, (R)im.y);
     }
-    C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
-    for (int c = tid; c < T * (J - 1); c += nthreads) {  // right strip
-        const int r = c / (J - 1), col = T + c - r * (J - 1);
-        halo[c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+    // Right strip: J - 1 cells of each row, rows tps (J - 1) apart.
+    C<R> *right = a.halo + halo_right(T, J, a.tps, t / a.tps, 0, t % a.tps);
+    const int rstride = a.tps * (J - 1);
+    for (int c = tid; c < T * (J - 1); c += nthreads) {
+        const int r = c / (J - 1), jj = c - r * (J - 1);
+        right[(int64_t)r * rstride + jj] = mk<R>((R)tre[r * RS + T + jj], (R)tim[r * RS + T + jj]);
     }
+    C<R> *bottom = a.halo + halo_bottom(T, J, a.tps, t);
     const int W = T + J - 1;
     const float inv = 1.0f / (float)W;
     for (int c = tid; c < (J - 1) * W; c += nthreads) {  // bottom strip with the corner
         const int q = (int)(((float)c + 0.5f) * inv);
         const int r = T + q, col = c - q * W;
-        halo[T * (J - 1) + c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
+        bottom[c] = mk<R>((R)tre[r * RS + col], (R)tim[r * RS + col]);
     }
 }
 
@@ -537,8 +551,13 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
             const int r = c >> lt;
             a.grid[(int64_t)(ta0 + r) * K + tb0 + (c & (T - 1))] = mk<R>(0, 0);
         }
-        C<R> *halo = a.halo + (int64_t)t * halo_cells(T, J);
-        for (int c = tid; c < halo_cells(T, J); c += kThreads) halo[c] = mk<R>(0, 0);
+        C<R> *right = a.halo + halo_right(T, J, tps, t / tps, 0, t % tps);
+        for (int c = tid; c < T * (J - 1); c += kThreads) {
+            const int r = c / (J - 1);
+            right[(int64_t)r * tps * (J - 1) + c - r * (J - 1)] = mk<R>(0, 0);
+        }
+        C<R> *bottom = a.halo + halo_bottom(T, J, tps, t);
+        for (int c = tid; c < (J - 1) * (T + J - 1); c += kThreads) bottom[c] = mk<R>(0, 0);
         return;
     }
     const int ta = (t / tps) * T, tb = (t % tps) * T;
@@ -865,12 +884,11 @@ __global__ void grid_merge(C<R> *grid, const C<R> *halo, int K, int T, int J, in
     const int up = ((dr + tps - 1) % tps) * tps + dc;
     const int left = dr * tps + (dc + tps - 1) % tps;
     const int ul = ((dr + tps - 1) % tps) * tps + (dc + tps - 1) % tps;
-    const int HC = halo_cells(T, J);
     const int64_t cell = (int64_t)(dr * T + i) * K + dc * T + j;
     C<R> v = grid[cell];
-    if (i < J - 1) v = cadd<R>(v, halo[(int64_t)up * HC + T * (J - 1) + i * (T + J - 1) + j]);
-    if (j < J - 1) v = cadd<R>(v, halo[(int64_t)left * HC + i * (J - 1) + j]);
-    if (i < J - 1 && j < J - 1) v = cadd<R>(v, halo[(int64_t)ul * HC + T * (J - 1) + i * (T + J - 1) + T + j]);
+    if (i < J - 1) v = cadd<R>(v, halo[halo_bottom(T, J, tps, up) + i * (T + J - 1) + j]);
+    if (j < J - 1) v = cadd<R>(v, halo[halo_right(T, J, tps, dr, i, left % tps) + j]);
+    if (i < J - 1 && j < J - 1) v = cadd<R>(v, halo[halo_bottom(T, J, tps, ul) + i * (T + J - 1) + T + j]);
     grid[cell] = v;
 }
 

@@ -382,18 +382,18 @@ fft_pass_p2(FftArgs<R> a) {
         if constexpr (!COLS) {
             // Gridding halos: a tile's first J - 1 rows and columns receive
             // what the tiles above, to the left and above-left left in their
-            // halo slots (bottom strip (J - 1) x (T + J - 1) after a right
-            // strip T x (J - 1)), added in that order.  The row's left and
-            // above-left parts (J - 1 values per tile, at a stride W = 8 or
-            // 16 per tile) are first gathered into this row's LDS line, which
-            // the first exchange overwrites only after its leading barrier;
-            // host side: 2 W tps <= N, so each thread gathers at most 4.
+            // halo cells, added in that order.  The row's left and above-left
+            // parts (J - 1 values per tile) are first gathered into this
+            // row's LDS line at a stride W = 8 or 16 per tile, which the
+            // first exchange overwrites only after its leading barrier; host
+            // side: 2 W tps <= N, so each thread gathers at most 4.
             if (a.halo) {
                 const int T = a.hT, J1 = a.hJ - 1, tps = a.htps, lt = __builtin_ctz(T);
                 const int lw = J1 <= 8 ? 3 : 4, NL = tps << lw;
-                // Halo layout (gridding): right strips by grid row, row k1's
-                // tps (J - 1) cells contiguous, then the bottom strips tile by
-                // tile, BC = (J - 1)(T + J - 1) cells each.
+                // Halo layout (gridding): the right strips by grid row, so
+                // the left parts of row k1 are one contiguous run of
+                // tps (J - 1) cells; then the bottom strips (with the corner)
+                // tile by tile, BC = (J - 1)(T + J - 1) cells each.
                 const int BC = J1 * (T + J1);
                 const int k1 = (int)t, dr = k1 >> lt, i = k1 & (T - 1);
                 const int upr = dr == 0 ? tps - 1 : dr - 1;

@@ -285,7 +285,7 @@ bool launch_phi_fft_adjoint(riop_plan *p, void *x, hipStream_t st, const void *g
 // out_grid = G^T G in_grid (fused degrid + grid, the Gram part of Phi^dagger Phi).
 // Throws RIOP_ENOTSUP if the plan's gridding tile needs more LDS than the device has.
 void check_grid_lds(riop_plan *p);
-// Complex cells of one tile's gridding halo slot.
+// Complex halo cells of one gridding tile (right strip and bottom strip).
 inline int grid_halo_cells(int T, int J) { return T * (J - 1) + (J - 1) * (T + J - 1); }
 template <typename R> void launch_gram(riop_plan *p, const void *in_grid, void *out_grid, hipStream_t st);
 // Precomputed G^T G: planes per offset for width J, build (synchronises) and apply.

@@ -23,7 +23,7 @@
 // 8-aligned column block are summed in registers, on the matrix cores where
 // possible, and closed with LDS double atomic adds: floating-point LDS
 // atomics in single precision are slow on this GPU), then stores its own
-// cells to the grid and the rest to a halo slot; a second kernel adds each
+// cells to the grid and the rest to its halo cells; a second kernel adds each
 // tile's three incoming halos.  No zeroing of the grid, no global atomics,
 // and every visibility is read once.
 //
@@ -449,7 +449,7 @@ template <typename R> struct TileArgs {
     const double *p2scale;    // min(1, eps / ||v - y||), one value
 };
 
-// Own cells of tile t to the grid, the rest of its region to its halo slot.
+// Own cells of tile t to the grid, the rest of its region to its halo cells.
 // T is a power of two (shifts and masks); the bottom strip's row is found by
 // a single-precision reciprocal, exact here: cell index and strip width are
 // small integers, so (c + 1/2) / W stays at least 1 / (2 W) away from the
@@ -509,7 +509,7 @@ __device__ inline void store_region(const TileArgs<R> &a, const double *tre, con
 // reads only what it staged itself.
 //
 // The workgroup finally stores its own T x T cells to the grid and the rest
-// of the region to its halo slot; the adjoint FFT's row pass adds the halos
+// of the region to its halo cells; the adjoint FFT's row pass adds the halos
 // of the three neighbours a tile receives from as it loads the grid (or
 // grid_merge does, where that pass is not the specialised one).
 // WAVES: grid_waves<R>(J), or 2 for tiles whose region leaves too little LDS.
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
 
     const WorkUnit wk = a.order[blockIdx.x];
     const int t = wk.tile, v0 = wk.start, total = wk.count;
-    if (total == 0) {  // an empty tile: zeros for its cells and its halo slot, no region
+    if (total == 0) {  // an empty tile: zeros for its cells and its halo cells, no region
         const int ta0 = (t / tps) * T, tb0 = (t % tps) * T, lt = __builtin_ctz(T);
         for (int c = tid; c < T * T; c += kThreads) {
             const int r = c >> lt;
@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(64 * WAVES) grid_tile(TileArgs<R> a) {
 }
 
 // Adds to each tile's first J-1 rows and columns what the tiles above, to
-// the left and above-left left in their halo slots (periodic in the tile
+// the left and above-left left in their halo cells (periodic in the tile
 // grid), in that fixed order.  One thread per border cell.  The adjoint FFT's
 // specialised row pass performs the same additions, in the same order, on
 // load; this kernel serves the other FFT lengths.

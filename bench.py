@@ -102,13 +102,13 @@ def traffic_summary(fetch_dir, write_dir, probe_mib):
     total = sum(out[c]["tile"] + out[c]["merge"] for c in out)
     lines = ["# HBM traffic of the FP32 gridding launch, 1024^2, M = 4194304, J = 8 (grid_tile; grid_merge only where the "
              "adjoint FFT does not add the halos itself)\n",
-             "Commands (repository root on the MI355X host, one counter pass each):\n", "```",
+             "Commands (repository root on the MI355X host, one counter pass each; $OUT is any writable folder):\n", "```",
              "cd /tmp && export TMPDIR=/tmp",
-             f"timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_fetch -o t -- "
+             f"timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o t -- "
              f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --no-batch --no-extras --copy-probe {probe_mib}",
-             f"timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_write -o t -- "
+             f"timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o t -- "
              f"python3 $REPO/bench.py --steps 1 --warmup 1 --pairs 2 --no-cpu-baseline --no-fp64 --no-graph --no-batch --no-extras --copy-probe {probe_mib}",
-             f"python3 $REPO/bench.py --traffic-summary $REPO/gpurun_out/pmc_fetch $REPO/gpurun_out/pmc_write "
+             f"python3 $REPO/bench.py --traffic-summary $OUT/pmc_fetch $OUT/pmc_write "
              f"--copy-probe {probe_mib}", "```\n",
              f"Calibration: a plain {probe_mib} MiB device copy; its counter reading is scaled to exactly "
              f"{probe_mib} MiB read and written.\n",

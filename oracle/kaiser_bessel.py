@@ -1,7 +1,7 @@
 """Kaiser-Bessel interpolation kernel for the gridding matrix G (oracle, FP64).
 
 The paper's package uses a compact-support Gaussian kernel for G and says other
-kernels can be used (Sec. 5, discussion of eq. opmodel).  This build uses the
+kernels can be used (Sec. 5, discussion of eq. opmodel).  Here G uses the
 Kaiser-Bessel kernel of width J grid cells with the shape parameter rule of
 Beatty, Nishimura & Pauly (2005) for oversampling alpha = 2:
 

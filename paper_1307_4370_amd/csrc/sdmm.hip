@@ -148,6 +148,21 @@ template <typename R> __global__ void cg_pq(const C<R> *p, C<R> *qp, long N, dou
 template <typename R>
 __global__ void cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long N, double *partials, int slot_old,
                           int slot_pq, int slot_new, double *scalars, double tol2, int first) {
+    // The first chunk's loads are issued before the partial sums are read,
+    // so that the two latencies overlap.
+    const long st = (long)gridDim.x * blockDim.x;
+    long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    C<R> pv[kU], qv[kU], xv[kU], rv[kU];
+    auto load = [&](long b) {
+        FOR_U(u) if (b + u * st < N) {
+            const long i = b + u * st;
+            pv[u] = p[i];
+            qv[u] = qp[i];
+            xv[u] = x[i];
+            rv[u] = r[i];
+        }
+    };
+    load(i0);
     const double rr = slot_sum(partials, slot_old);
     const double pq = slot_sum(partials, slot_pq);
     const double rr0 = first ? rr : scalars[SC_RR0];
@@ -158,15 +173,8 @@ __global__ void cg_update(C<R> *x, C<R> *r, const C<R> *p, const C<R> *qp, long 
         if (alpha != 0.0) scalars[SC_CGIT] += 1.0;
     }
     double acc = 0;
-    CHUNK_LOOP(i0, st, N) {
-        C<R> pv[kU], qv[kU], xv[kU], rv[kU];
-        FOR_U(u) if (i0 + u * st < N) {
-            const long i = i0 + u * st;
-            pv[u] = p[i];
-            qv[u] = qp[i];
-            xv[u] = x[i];
-            rv[u] = r[i];
-        }
+    for (bool head = true; i0 < N; i0 += kU * st, head = false) {
+        if (!head) load(i0);
         FOR_U(u) if (i0 + u * st < N) {
             const long i = i0 + u * st;
             C<R> xi = xv[u], ri = rv[u];
